@@ -1,0 +1,189 @@
+"""Benchmark: D3Q19 colour-gradient step at 256^3 in FP32 on one MI355X.
+
+One step = the whole hot path (moments, isotropic gradients, BGK with the
+enhanced equilibrium, perturbation, recolouring, streaming) over the whole
+lattice.  Input: 32 seeded non-overlapping droplets (radii U[10, 24]) in a
+periodic 256^3 box, density ratio 1, tau = 1, A = 0.005, beta = 0.7.
+
+Prints one JSON line with MLUPS, the HBM roofline fraction of the step kernel
+(algorithmic 304 B per lattice update / measured kernel time, against 8 TB/s)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 CG MLUPS + % HBM roofline at 256^3; sweep-serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["node.hpp", "kernels.hpp", "fused.hpp", "lattice.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_05197_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name: str, per_launch_units: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_fused_cg_d3q19_fp32_256.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    vals = {}
+    for line in txt.splitlines():
+        if line.startswith("|") and ":" not in line:
+            continue
+        for key in ("kernel_sources_sha256_16", "hbm_bytes_per_launch"):
+            if line.strip().startswith(key + ":"):
+                vals[key] = line.split(":", 1)[1].strip()
+    if vals.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def workload_fields(n: int, seed: int = 0):
+    from paper_2110_05197_amd import inputs
+    rR, rB, placed = inputs.random_droplets((n, n, n), 32 if n >= 128 else 4,
+                                            10.0 * n / 256, 24.0 * n / 256, seed)
+    return rR, rB
+
+
+def params(n: int, precision: int = 1, kernel: int = 0):
+    import paper_2110_05197_amd as M
+    return M.make_params(lattice=M.D3Q19, model=M.CG, precision=precision, nx=n, ny=n, nz=n,
+                         rho0_R=1.0, rho0_B=1.0, tau_R=1.0, tau_B=1.0, A=0.005, beta=0.7,
+                         kernel=kernel)
+
+
+def cpu_baseline(rR, rB, n: int, steps: int):
+    """The FP64 oracle (as it stands, OpenMP over the host cores) on `steps`
+    steps of the same fields."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+    oracle.build(force=False)
+    p = oracle.make_params(lattice=1, model=0, nx=n, ny=n, nz=n, rho0_R=1.0, rho0_B=1.0,
+                           tau_R=1.0, tau_B=1.0, A=0.005, beta=0.7)
+    f = oracle.init_equilibrium(p, rR, rB)
+    t0 = time.perf_counter()
+    f = oracle.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    del f
+    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"FP64 oracle, D3Q19 CG {n}^3 of the same 32-droplet fields, {steps} steps "
+                       f"({dt:.1f} s wall)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--precision", type=int, default=1, help="0 FP64, 1 FP32, 2 mixed, 3 FP16")
+    ap.add_argument("--kernel", type=int, default=0, help="0 auto (fused), 1 two-pass, 2 fused")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU slab decomposition is a design, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2110_05197_amd as M
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    n = args.size
+    print(f"[bench] generating {n}^3 fields", file=sys.stderr, flush=True)
+    rR, rB = workload_fields(n)
+    p = params(n, args.precision, args.kernel)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB)
+    stream = torch.cuda.current_stream()
+    o0 = sim.observables()
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    st, done = sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ms = ms_total / args.steps
+    o1 = sim.observables()
+    N = n ** 3
+    mlups = N / (ms * 1e-3) / 1e6
+    bpu = M.bytes_per_update(p)
+    achieved = bpu * N / (ms * 1e-3) / 1e9
+    fused = sim.params.get("kernel", 0) != 1
+    drift = abs(o1["mass_R"] - o0["mass_R"]) / o0["mass_R"]
+    print(f"[bench] {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, "
+          f"mass drift {drift:.2e}, diverged={o1['diverged']}", file=sys.stderr, flush=True)
+    traffic = measured_traffic("k_fused", N) if (fused and args.precision == 1 and n == 256) else None
+    del sim
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline ({args.cpu_steps} oracle steps)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(rR, rB, n, args.cpu_steps)
+
+    dtype = {0: "f64", 1: "f32", 2: "f32+f64", 3: "f16-storage/f32"}[args.precision]
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"D3Q19 colour-gradient step, {n}^3 periodic, 32 seeded droplets r~U[10,24], "
+                        "gamma=1, tau=1, A=0.005, beta=0.7",
+            "lattice": "D3Q19", "model": "CG", "nx": n, "ny": n, "nz": n,
+            "precision": dtype, "kernel": "fused one-pass" if fused else "two-pass",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_update": bpu,
+        },
+        "cpu_baseline": cpu,
+        "mass_drift": drift,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

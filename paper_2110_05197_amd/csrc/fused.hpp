@@ -1,0 +1,303 @@
+// fused.hpp -- one-pass D3Q19 step: each block owns a TX x TY column of
+// nodes and marches it through a chunk of TZ planes.  The stencil inputs
+// (colour-gradient densities / pseudopotential) of plane z+1 are computed
+// from the populations as they are loaded, for the tile and a one-node x-y
+// halo ring, into a three-plane LDS ring; the tile's own populations stay in
+// registers from the load of plane z+1 to the collision of that plane one
+// iteration later.  Only the halo ring's populations are read twice (by this
+// block and its neighbour), so HBM traffic stays near one read and one write
+// of every population per step; no density field is written.
+//
+// Requires nx % TX == 0 and ny % TY == 0 (the host falls back to the
+// two-pass kernels otherwise); any nz.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace mclbm {
+
+// Stencil-field values of one node from its populations (the same values the
+// density-field pass stores).
+template <int MODEL, int NF, class C, class M, class FT>
+__device__ __forceinline__ void field_values(const HP<C, M> &H, const M (&dr)[2], FT (&v)[NF])
+{
+    if constexpr (MODEL == CG) {
+        v[0] = (FT)dr[0];
+        v[1] = (FT)dr[1];
+        v[2] = (FT)colour_field(H, dr[0], dr[1]);
+    } else if constexpr (MODEL == SC_MP) {
+        v[0] = (FT)pseudo_potential(H, H.rho0[0] + dr[0]);
+    } else {
+        v[0] = (FT)dr[0];
+        v[1] = (FT)dr[1];
+    }
+}
+
+// Block index -> tile, keeping runs of consecutive tiles on one XCD (blocks
+// are dealt round-robin to the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    if (nblocks % 8) return b;
+    return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+template <int MODEL, int TX, int TY, class FT>
+constexpr int fused_ring_bytes()
+{
+    return (4 * NField<MODEL>::n * (TX + 2) * (TY + 2) * (int)sizeof(FT) + 15) / 16 * 16;
+}
+template <int PR, int MODEL, int TX, int TY>
+constexpr int fused_lds_bytes()
+{
+    return fused_ring_bytes<MODEL, TX, TY, typename Prec<PR>::F>()
+           + NComp<MODEL>::n * D3Q19::Q * TX * TY * (int)sizeof(typename Prec<PR>::C);
+}
+
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC>
+__global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec<PR>::S *__restrict__ src,
+                                                  typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int TZ,
+                                                  int tiles_x, int tiles_y)
+{
+    using L = D3Q19;
+    using C = typename Prec<PR>::C;
+    using M = typename Prec<PR>::M;
+    using FT = typename Prec<PR>::F;
+    constexpr int Q = L::Q;
+    constexpr int K = NComp<MODEL>::n;
+    constexpr int NF = NField<MODEL>::n;
+    constexpr int HX = TX + 2, HY = TY + 2, PL = HX * HY, NT = TX * TY, NH = PL - NT;
+    static_assert(NH <= NT, "halo ring larger than the block");
+    // Dynamic LDS: a four-plane ring of stencil values (planes z-1, z, z+1
+    // are read while plane z+2 is written), then each thread's private slot
+    // holding the populations of plane z+1 (laid out [population][thread] so
+    // that a wavefront's accesses are contiguous).
+    extern __shared__ __align__(16) unsigned char smem[];
+    FT (*lds)[NF][PL] = reinterpret_cast<FT (*)[NF][PL]>(smem);
+    C *pop = reinterpret_cast<C *>(smem + fused_ring_bytes<MODEL, TX, TY, FT>());
+
+    const long long N = P.N;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const HP<C, M> H = make_hp<C, M>(P);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int z1 = min(z0 + TZ, nz);
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const int my_slot = (ly + 1) * HX + (lx + 1);
+
+    // halo ring node of this thread: rows y0-1 and y0+TY, then columns
+    // x0-1 and x0+TX
+    const bool has_h = tid < NH;
+    int hx = 0, hy = 0;
+    if (tid < HX) { hx = tid - 1; hy = -1; }
+    else if (tid < 2 * HX) { hx = tid - HX - 1; hy = TY; }
+    else if (tid < 2 * HX + TY) { hx = -1; hy = tid - 2 * HX; }
+    else { hx = TX; hy = tid - 2 * HX - TY; }
+    const int h_slot = (hy + 1) * HX + (hx + 1);
+    const int hgx = stencil_coord(x0 + hx, nx, P.bc[0]);
+    const int hgy = stencil_coord(y0 + hy, ny, P.bc[1]);
+    const long long n_xy = (long long)x + (long long)nx * y;
+    const long long h_xy = (long long)hgx + (long long)nx * hgy;
+    const long long sxy = (long long)nx * ny;
+    auto ring = [&](int p) { return (p - z0 + 1) & 3; };
+
+    bool bad = false;
+    // stencil values of one node of plane p from its populations
+    auto put = [&](int p, int slot, const C (&gv)[K][Q], M (&drv)[2], M (&jv)[3], bool interior) {
+        node_moments<L, K>(gv, drv, jv);
+        FT v[NF];
+        field_values<MODEL, NF>(H, drv, v);
+#pragma unroll
+        for (int a = 0; a < NF; ++a) lds[ring(p)][a][slot] = v[a];
+        if (interior && p >= z0 && p < z1) {
+            const M r = H.rho0[0] + drv[0] + (K == 2 ? H.rho0[1] + drv[1] : M(0));
+            bad = bad || node_bad(r, jv[0] + jv[1] + jv[2]);
+        }
+    };
+    auto zoff = [&](int p) { return sxy * stencil_coord(p, nz, P.bc[2]); };
+
+    C c[K][Q];                  // populations of plane z (plane z+1's wait in LDS)
+    M drc[2], jc[3], drn[2], jn[3];
+    {
+        // prologue: stencil values of planes z0-1, z0, z0+1; populations of z0, z0+1
+        C tmp[K][Q];
+        M d2[2], j2[3];
+        load_node<L, K>(src, N, n_xy + zoff(z0 - 1), tmp);
+        put(z0 - 1, my_slot, tmp, d2, j2, true);
+        load_node<L, K>(src, N, n_xy + zoff(z0), c);
+        put(z0, my_slot, c, drc, jc, true);
+        load_node<L, K>(src, N, n_xy + zoff(z0 + 1), tmp);
+        put(z0 + 1, my_slot, tmp, drn, jn, true);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) pop[(k * Q + i) * NT + tid] = tmp[k][i];
+        if (has_h)
+            for (int p = z0 - 1; p <= z0 + 1; ++p) {
+                load_node<L, K>(src, N, h_xy + zoff(p), tmp);
+                put(p, h_slot, tmp, d2, j2, false);
+            }
+    }
+    __syncthreads();
+
+    for (int z = z0; z < z1; ++z) {
+        // 1. issue the loads of plane z+2 (consumed after the collision)
+        const bool ahead = z + 2 <= z1;
+        C d[K][Q], hh[K][Q];
+        if (ahead) {
+            load_node<L, K>(src, N, n_xy + zoff(z + 2), d);
+            if (has_h) load_node<L, K>(src, N, h_xy + zoff(z + 2), hh);
+        }
+
+        // 2. collide plane z with the stencil values of planes z-1, z, z+1
+        {
+            C v[NF][Q];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int s = ring(z + L::cz[i]);
+                const int o = my_slot + L::cy[i] * HX + L::cx[i];
+#pragma unroll
+                for (int a = 0; a < NF; ++a) v[a][i] = (C)lds[s][a][o];
+            }
+#pragma unroll
+            for (int a = 0; a < NF; ++a) v[a][0] = C(0);
+
+            if constexpr (MODEL == CG) {
+                C gR[3], gB[3], gN[3];
+                stencil_sum<L>(v[0], gR);
+                stencil_sum<L>(v[1], gB);
+                stencil_sum<L>(v[NF - 1], gN);
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) { gR[dd] *= C(3); gB[dd] *= C(3); gN[dd] *= C(3); }
+                const C F0[3] = {C(0), C(0), C(0)};
+                cg_collide<L, C, M, false>(H, c, drc, jc, gR, gB, gN, F0);
+            } else if constexpr (MODEL == SC_MP) {
+                C s3[3];
+                stencil_sum<L>(v[0], s3);
+                const C psi = (C)lds[ring(z)][0][my_slot];
+                const M rho = H.rho0[0] + drc[0];
+                const M irho = rcp(rho);
+                C F[3], u[3];
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) {
+                    F[dd] = -H.G * psi * s3[dd];
+                    u[dd] = (C)((jc[dd] + M(0.5) * (M)F[dd]) * irho);
+                }
+                sc_collide_component<L, C, M>(c[0], H.om[0], drc[0], rho, u, F, H.rho0[0], H.corrM[0], H.shiftM[0]);
+            } else {
+                C sR[3], sB[3];
+                stencil_sum<L>(v[0], sR);
+                stencil_sum<L>(v[NF - 1], sB);
+                const M rR = H.rho0[0] + drc[0], rB = H.rho0[1] + drc[1];
+                const M ir = rcp(rR + rB);
+                C FR[3], FB[3], u[3];
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) {
+                    FR[dd] = -H.xpref * (C)rR * sB[dd];
+                    FB[dd] = -H.xpref * (C)rB * sR[dd];
+                    u[dd] = (C)((jc[dd] + M(0.5) * ((M)FR[dd] + (M)FB[dd])) * ir);
+                }
+                sc_collide_component<L, C, M>(c[0], H.om[0], drc[0], rR, u, FR, H.rho0[0], H.corrM[0], H.shiftM[0]);
+                sc_collide_component<L, C, M>(c[K - 1], H.om[1], drc[1], rB, u, FB, H.rho0[1], H.corrM[1], H.shiftM[1]);
+            }
+            const long long n = n_xy + sxy * z;
+            if constexpr (PERIODIC) push_store_periodic<L, K>(P, dst, x, y, z, n, c);
+            else push_store_general<L, K>(P, dst, x, y, z, n, c);
+        }
+
+        // 3. stencil values of plane z+2
+        M drd[2], jd[3];
+        if (ahead) {
+            put(z + 2, my_slot, d, drd, jd, true);
+            if (has_h) {
+                M dh[2], jh[3];
+                put(z + 2, h_slot, hh, dh, jh, false);
+            }
+        }
+        // 4. rotate through this thread's LDS slot: z+1 -> z, z+2 -> z+1
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                C *sl = &pop[(k * Q + i) * NT + tid];
+                c[k][i] = *sl;
+                *sl = d[k][i];
+            }
+        __syncthreads();  // plane z+2 complete; plane z-1's slot is free
+        drc[0] = drn[0]; drc[1] = drn[1];
+        jc[0] = jn[0]; jc[1] = jn[1]; jc[2] = jn[2];
+        drn[0] = drd[0]; drn[1] = drd[1];
+        jn[0] = jd[0]; jn[1] = jd[1]; jn[2] = jd[2];
+    }
+    const unsigned long long any = __ballot(bad);
+    if (any != 0ull && (tid & 63) == 0) atomicOr(flag, 1u);
+}
+
+struct FusedShape {
+    int tx, ty, tz;
+};
+
+// Tile choice: TX = 64 when nx allows, else 32; TY the largest of 8, 4, 2, 1
+// dividing ny; TZ planes per block.
+inline bool fused_shape(const KParams &P, FusedShape &sh)
+{
+    if (P.nx % 64 == 0) sh.tx = 64;
+    else if (P.nx % 32 == 0) sh.tx = 32;
+    else return false;
+    sh.ty = 0;
+    const int cand[2] = {8, 4};
+    for (int c : cand)
+        if (P.ny % c == 0 && (sh.tx + 2) * (c + 2) - sh.tx * c <= sh.tx * c) { sh.ty = c; break; }
+    if (!sh.ty) return false;
+    // z-chunk: about one block per compute unit (256 on MI355X) -- more
+    // resident blocks per XCD overflow its L2 and the halo re-reads miss
+    const long long txy = (long long)(P.nx / sh.tx) * (P.ny / sh.ty);
+    const long long tiles_z = std::max<long long>(1, (256 + txy - 1) / txy);
+    sh.tz = (int)((P.nz + tiles_z - 1) / tiles_z);
+    return true;
+}
+
+template <int PR, int MODEL, int TX, int TY>
+void launch_fused_shape(const KParams &P, const void *src, void *dst, unsigned *flag, int tz, hipStream_t s)
+{
+    const int tiles_x = P.nx / TX, tiles_y = P.ny / TY, tiles_z = (P.nz + tz - 1) / tz;
+    const dim3 grid(tiles_x * tiles_y * tiles_z), block(TX * TY);
+    using S = typename Prec<PR>::S;
+    constexpr int lds = fused_lds_bytes<PR, MODEL, TX, TY>();
+    static bool attr_set = false;   // raise the dynamic-LDS limit once per process
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr_set = true;
+    }
+    if (P.bc[0] == 0 && P.bc[1] == 0 && P.bc[2] == 0)
+        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, true>), grid, block, lds, s, P, (const S *)src, (S *)dst,
+                           flag, tz, tiles_x, tiles_y);
+    else
+        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, false>), grid, block, lds, s, P, (const S *)src, (S *)dst,
+                           flag, tz, tiles_x, tiles_y);
+}
+
+template <int PR, int MODEL>
+void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s)
+{
+    FusedShape sh;
+    fused_shape(P, sh);  // checked at create time
+    if (sh.tx == 64) {
+        if (sh.ty == 8) launch_fused_shape<PR, MODEL, 64, 8>(P, src, dst, flag, sh.tz, s);
+        else launch_fused_shape<PR, MODEL, 64, 4>(P, src, dst, flag, sh.tz, s);
+    } else {
+        if (sh.ty == 8) launch_fused_shape<PR, MODEL, 32, 8>(P, src, dst, flag, sh.tz, s);
+        else launch_fused_shape<PR, MODEL, 32, 4>(P, src, dst, flag, sh.tz, s);
+    }
+}
+
+}  // namespace mclbm

@@ -1,0 +1,52 @@
+// lattice.hpp -- D2Q9 and D3Q19 velocity sets and the colour-gradient
+// constants, as compile-time tables for the device code.
+//
+// D3Q19 (arXiv:2110.05197, section 2): velocities Eq. speeds, weights
+// Eq. weights, perturbation constants B_i (after Eq. perturbationOp),
+// enhanced-equilibrium constants psi_i and xi_i (after Eq. phi) and the rest
+// fractions phi_i(alpha) of Eq. phi: alpha, (1-alpha)/12, (1-alpha)/24.
+// D2Q9 is not in the paper; its constants satisfy the same moment
+// conditions: phi alpha, (1-alpha)/5, (1-alpha)/20; B -4/27, 2/27, 5/108;
+// psi -8/3, -1/6, 1/12; xi 0, 1/2, 1/8.
+//
+// Ordering: 0 = rest, then opposite pairs (i, i+1) for odd i, axis
+// directions before diagonals.  The "group" of a direction is |c|^2 (0, 1, 2).
+#pragma once
+
+namespace mclbm {
+
+struct D2Q9 {
+    static constexpr int D = 2;
+    static constexpr int Q = 9;
+    static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int grp[9] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
+    // per group: rest, axis, diagonal
+    static constexpr double w[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+    static constexpr double B[3] = {-4.0 / 27.0, 2.0 / 27.0, 5.0 / 108.0};
+    static constexpr double psi[3] = {-8.0 / 3.0, -1.0 / 6.0, 1.0 / 12.0};
+    static constexpr double xi[3] = {0.0, 0.5, 0.125};
+    // phi(alpha) = phi_a * alpha + phi_b
+    static constexpr double phi_a[3] = {1.0, -0.2, -0.05};
+    static constexpr double phi_b[3] = {0.0, 0.2, 0.05};
+    static constexpr double inv_len[3] = {0.0, 1.0, 0.70710678118654752440};
+};
+
+struct D3Q19 {
+    static constexpr int D = 3;
+    static constexpr int Q = 19;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int grp[19] = {0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+    static constexpr double w[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    static constexpr double B[3] = {-2.0 / 9.0, 1.0 / 54.0, 1.0 / 27.0};
+    static constexpr double psi[3] = {-2.5, -1.0 / 6.0, 1.0 / 24.0};
+    static constexpr double xi[3] = {0.0, 0.25, 0.125};
+    static constexpr double phi_a[3] = {1.0, -1.0 / 12.0, -1.0 / 24.0};
+    static constexpr double phi_b[3] = {0.0, 1.0 / 12.0, 1.0 / 24.0};
+    static constexpr double inv_len[3] = {0.0, 1.0, 0.70710678118654752440};
+};
+
+}  // namespace mclbm

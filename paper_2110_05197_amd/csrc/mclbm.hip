@@ -1,0 +1,754 @@
+// mclbm.hip -- C ABI (include/mclbm.h) of the two-component lattice
+// Boltzmann library: parameter validation, state layout on caller memory,
+// dispatch to the kernel instantiations, observables, checkpoints and the
+// batched stepping used for sweep serving.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mclbm.h"
+#include "fused.hpp"
+#include "ops.hpp"
+
+using namespace mclbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mclbm_status fail(mclbm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define MCLBM_HIP(expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(MCLBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int lattice_Q(int lattice) { return lattice == MCLBM_D2Q9 ? 9 : 19; }
+int ncomp_of(int model) { return model == MCLBM_SC_MP ? 1 : 2; }
+int nfield_of(int model) { return model == MCLBM_CG ? 3 : (model == MCLBM_SC_MP ? 1 : 2); }
+size_t storage_size(int prec) { return prec == MCLBM_FP64 ? 8 : (prec == MCLBM_FP16 ? 2 : 4); }
+size_t field_size(int prec) { return prec == MCLBM_FP64 ? 8 : 4; }
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t fbytes, field_off, gfield_off, total;
+};
+
+Layout layout_of(const mclbm_params &p)
+{
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    Layout L;
+    L.fbytes = align256((size_t)ncomp_of(p.model) * lattice_Q(p.lattice) * N * storage_size(p.precision));
+    L.field_off = 2 * L.fbytes;
+    L.gfield_off = L.field_off + align256((size_t)nfield_of(p.model) * N * field_size(p.precision));
+    const bool rep = p.model == MCLBM_CG && p.Pi != 0.0;
+    L.total = L.gfield_off + (rep ? align256(3 * N * field_size(p.precision)) : 0);
+    return L;
+}
+
+KParams make_kparams(const mclbm_params &p);
+
+bool fused_ok(const mclbm_params &p, const Ops *ops)
+{
+    FusedShape sh;
+    return ops && ops->has_fused() && fused_shape(make_kparams(p), sh);
+}
+
+mclbm_status validate(const mclbm_params *p)
+{
+    if (!p) return fail(MCLBM_EINVAL, "params is NULL");
+    if (p->abi_version != MCLBM_ABI_VERSION)
+        return fail(MCLBM_EINVAL, "abi_version %d, library has %d", p->abi_version, MCLBM_ABI_VERSION);
+    if (p->lattice != MCLBM_D2Q9 && p->lattice != MCLBM_D3Q19) return fail(MCLBM_EINVAL, "bad lattice %d", p->lattice);
+    if (p->model < 0 || p->model > 2) return fail(MCLBM_EINVAL, "bad model %d", p->model);
+    if (p->precision < 0 || p->precision > 3) return fail(MCLBM_EINVAL, "bad precision %d", p->precision);
+    if (p->nx < 2 || p->ny < 2) return fail(MCLBM_EINVAL, "nx, ny must be >= 2 (got %d, %d)", p->nx, p->ny);
+    if (p->lattice == MCLBM_D2Q9 && p->nz != 1) return fail(MCLBM_EINVAL, "D2Q9 needs nz == 1");
+    if (p->lattice == MCLBM_D3Q19 && p->nz < 2) return fail(MCLBM_EINVAL, "D3Q19 needs nz >= 2");
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    if (N > (1LL << 34)) return fail(MCLBM_EINVAL, "lattice too large");
+    for (int d = 0; d < 3; ++d)
+        if (p->bc[d] < 0 || p->bc[d] > 2) return fail(MCLBM_EINVAL, "bad boundary type on axis %d", d);
+    if (p->lattice == MCLBM_D2Q9 && p->bc[2] != MCLBM_PERIODIC) return fail(MCLBM_EINVAL, "D2Q9: bc[2] must be periodic");
+    if (!(p->tau_R > 0.5)) return fail(MCLBM_EINVAL, "tau_R must be > 1/2");
+    if (p->model != MCLBM_SC_MP && !(p->tau_B > 0.5)) return fail(MCLBM_EINVAL, "tau_B must be > 1/2");
+    if (!(p->rho0_R > 0.0)) return fail(MCLBM_EINVAL, "rho0_R must be > 0");
+    if (p->model == MCLBM_CG) {
+        if (!(p->rho0_B > 0.0) || p->rho0_B > p->rho0_R)
+            return fail(MCLBM_EINVAL, "CG needs 0 < rho0_B <= rho0_R (red is the denser fluid)");
+        if (!(p->beta >= 0.0 && p->beta <= 1.0)) return fail(MCLBM_EINVAL, "beta must be in [0, 1]");
+        if (!(p->alpha_B >= 0.0 && p->alpha_B < 1.0)) return fail(MCLBM_EINVAL, "alpha_B must be in [0, 1)");
+        if (!(p->A >= 0.0)) return fail(MCLBM_EINVAL, "A must be >= 0");
+        if (!(p->g_min >= 0.0)) return fail(MCLBM_EINVAL, "g_min must be >= 0");
+        if (p->Pi != 0.0 && !(p->chi > 0.0)) return fail(MCLBM_EINVAL, "repulsion needs chi > 0");
+    } else {
+        if (p->Pi != 0.0) return fail(MCLBM_EUNSUPPORTED, "the repulsion force is a colour-gradient variant");
+        if (p->model == MCLBM_SC_MP && !(p->psi_rho0 > 0.0)) return fail(MCLBM_EINVAL, "psi_rho0 must be > 0");
+        if (p->model == MCLBM_SC_MC && (!(p->rho0_B > 0.0) || !(p->rho0_X > 0.0)))
+            return fail(MCLBM_EINVAL, "SC_MC needs rho0_B > 0 and rho0_X > 0");
+    }
+    if (p->kernel < 0 || p->kernel > 2) return fail(MCLBM_EINVAL, "bad kernel choice %d", p->kernel);
+    const Ops *ops = get_ops(p->lattice, p->precision, p->model, p->model == MCLBM_CG && p->Pi != 0.0);
+    if (!ops) return fail(MCLBM_EUNSUPPORTED, "combination not provided");
+    if (p->kernel == MCLBM_KERNEL_FUSED && !fused_ok(*p, ops))
+        return fail(MCLBM_EUNSUPPORTED, "no fused kernel for this lattice/model/precision/size");
+    return MCLBM_OK;
+}
+
+template <class L>
+void fill_phi(const mclbm_params &p, KParams &K)
+{
+    if (p.model == MCLBM_CG) {
+        const double aB = p.alpha_B;
+        const double aR = 1.0 - (1.0 - aB) * p.rho0_B / p.rho0_R;  // Eq. gamma
+        for (int q = 0; q < 3; ++q) {
+            K.phi[0][q] = L::phi_a[q] * aR + L::phi_b[q];
+            K.phi[1][q] = L::phi_a[q] * aB + L::phi_b[q];
+        }
+    } else {
+        for (int q = 0; q < 3; ++q) K.phi[0][q] = K.phi[1][q] = L::w[q];
+    }
+}
+
+KParams make_kparams(const mclbm_params &p)
+{
+    KParams K;
+    memset(&K, 0, sizeof K);
+    K.nx = p.nx; K.ny = p.ny; K.nz = p.nz;
+    for (int d = 0; d < 3; ++d) K.bc[d] = p.bc[d];
+    K.N = (long long)p.nx * p.ny * p.nz;
+    K.enhanced = p.enhanced_eq ? 1 : 0;
+    K.has_outflow = (p.bc[0] == MCLBM_OUTFLOW || p.bc[1] == MCLBM_OUTFLOW || p.bc[2] == MCLBM_OUTFLOW) ? 1 : 0;
+    K.rho0[0] = p.rho0_R;
+    K.rho0[1] = p.model == MCLBM_SC_MP ? 0.0 : p.rho0_B;
+    if (p.lattice == MCLBM_D2Q9) fill_phi<D2Q9>(p, K); else fill_phi<D3Q19>(p, K);
+    const int Q = lattice_Q(p.lattice);
+    const int count[3] = {1, p.lattice == MCLBM_D2Q9 ? 4 : 6, p.lattice == MCLBM_D2Q9 ? 4 : 12};
+    (void)Q;
+    for (int k = 0; k < 2; ++k) {
+        for (int q = 0; q < 3; ++q) K.shift[k][q] = K.rho0[k] * K.phi[k][q];
+        if (p.precision != MCLBM_FP64 && K.rho0[k] > 0.0) {
+            // Float paths: put the reference on a grid of step 2^(e-22), e =
+            // ceil(log2 rho0), so that every shift, every partial sum of
+            // shifts and their total are exact in FP32.  "Component absent"
+            // (g = -shift) then sums to rho = 0 exactly instead of a rounding
+            // residue of the same sign at every node.
+            const int e = (int)std::ceil(std::log2(K.rho0[k] * 1.01));
+            const double qnt = std::ldexp(1.0, e - 22);
+            double tot = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                K.shift[k][q] = std::nearbyint(K.shift[k][q] / qnt) * qnt;
+                tot += count[q] * K.shift[k][q];
+            }
+            K.rho0[k] = tot;
+        }
+        for (int q = 0; q < 3; ++q) K.corr[k][q] = K.rho0[k] * K.phi[k][q] - K.shift[k][q];
+    }
+    K.inv_nu[0] = 3.0 / (p.tau_R - 0.5);
+    K.inv_nu[1] = p.model == MCLBM_SC_MP ? K.inv_nu[0] : 3.0 / (p.tau_B - 0.5);
+    K.halfA = 0.5 * p.A;
+    K.beta = p.beta;
+    K.g_min = p.g_min;
+    K.om[0] = 1.0 / p.tau_R;
+    K.om[1] = p.model == MCLBM_SC_MP ? K.om[0] : 1.0 / p.tau_B;
+    K.G = p.G;
+    K.psi_rho0 = p.psi_rho0;
+    K.xpref = p.model == MCLBM_SC_MC ? p.G_RB / (p.rho0_X * p.rho0_X) : 0.0;
+    K.Pi = p.Pi;
+    K.chi = p.chi;
+    K.sc_mid = 0.5 * (p.rho0_R + p.rho0_B);
+    return K;
+}
+
+EpsTable eps_table()
+{
+    EpsTable e;
+    for (int m = 0; m < 10; ++m) e.e[m] = 1.0 - pow(0.1, m + 1);
+    return e;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// Launcher table: each precision's instantiations live in their own
+// translation unit (inst_p<P>.hip) so that they compile in parallel.
+// ------------------------------------------------------------------------
+namespace mclbm {
+const Ops *get_ops(int lattice, int precision, int model, bool rep)
+{
+    switch (precision) {
+    case 0: return ops_prec0(lattice, model, rep);
+    case 1: return ops_prec1(lattice, model, rep);
+    case 2: return ops_prec2(lattice, model, rep);
+    case 3: return ops_prec3(lattice, model, rep);
+    }
+    return nullptr;
+}
+}  // namespace mclbm
+
+namespace mclbm {
+
+__global__ void k_obs_final(const double *__restrict__ partials, int nblocks, double *__restrict__ out)
+{
+    const int a = threadIdx.x;
+    if (a >= kNAcc) return;
+    double v = partials[a];
+    for (int b = 1; b < nblocks; ++b) {
+        const double w = partials[(long long)b * kNAcc + a];
+        v = (a == 6 || a == 8) ? fmax(v, w) : v + w;
+    }
+    out[a] = v;
+}
+
+// Close one batch step: running simulations flip buffers and count the
+// step, then stop when diverged (flag seen during the step) or at target.
+__global__ void kb_advance(SimDesc *D, int nsims)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsims) return;
+    SimDesc &d = D[s];
+    if (d.state != 0) return;
+    d.cur ^= 1;
+    d.steps += 1;
+    if (*d.flag) d.state = 2;
+    else if (d.steps >= d.target) d.state = 1;
+}
+
+}  // namespace mclbm
+
+struct mclbm_sim {
+    mclbm_params prm;
+    KParams kp;
+    const Ops *ops;
+    Layout lay;
+    char *base;
+    void *f[2];
+    void *field;
+    void *gfield;
+    int cur;
+    int64_t step;
+    hipStream_t stream;
+    int device;
+    bool fused;
+    bool in_batch;
+    unsigned *d_flag;
+    double *d_partials;
+    double *d_obs;
+    double *h_obs;
+    unsigned *h_flag;
+};
+
+struct mclbm_batch {
+    std::vector<mclbm_sim *> sims;
+    std::vector<int> order;          // descriptor slot -> index into sims
+    std::vector<int64_t> step0;
+    hipStream_t stream;
+    SimDesc *d_desc;
+    SimDesc *h_desc;
+    struct Group {
+        const Ops *ops;
+        int first, count;
+        long long blocks, oblocks;
+        bool any_outflow;
+    };
+    std::vector<Group> groups;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int graph_k;
+};
+
+extern "C" {
+
+mclbm_status mclbm_version(int32_t *major, int32_t *minor)
+{
+    if (!major || !minor) return fail(MCLBM_EINVAL, "NULL argument");
+    *major = MCLBM_VERSION_MAJOR;
+    *minor = MCLBM_VERSION_MINOR;
+    return MCLBM_OK;
+}
+
+const char *mclbm_status_str(mclbm_status s)
+{
+    switch (s) {
+    case MCLBM_OK: return "ok";
+    case MCLBM_DIVERGED: return "diverged";
+    case MCLBM_EINVAL: return "invalid argument";
+    case MCLBM_EUNSUPPORTED: return "unsupported";
+    case MCLBM_EDEVICE: return "device error";
+    case MCLBM_ENOMEM: return "out of memory";
+    }
+    return "unknown status";
+}
+
+const char *mclbm_last_error(void) { return g_last_error.c_str(); }
+
+mclbm_status mclbm_params_default(mclbm_params *p, int32_t lattice, int32_t model)
+{
+    if (!p) return fail(MCLBM_EINVAL, "params is NULL");
+    memset(p, 0, sizeof *p);
+    p->abi_version = MCLBM_ABI_VERSION;
+    p->lattice = lattice;
+    p->model = model;
+    p->precision = MCLBM_FP32;
+    p->nx = p->ny = 64;
+    p->nz = lattice == MCLBM_D2Q9 ? 1 : 64;
+    p->bc[0] = p->bc[1] = p->bc[2] = MCLBM_PERIODIC;
+    p->enhanced_eq = 1;
+    p->kernel = MCLBM_KERNEL_AUTO;
+    p->rho0_R = 1.0;
+    p->rho0_B = 1.0;
+    p->tau_R = p->tau_B = 1.0;
+    p->A = 0.005;
+    p->beta = 0.7;
+    p->alpha_B = 0.2;
+    p->g_min = 1e-8;
+    p->G = -5.0;
+    p->psi_rho0 = 1.0;
+    p->G_RB = 0.9;
+    p->rho0_X = 1.0;
+    p->Pi = 0.0;
+    p->chi = 1.0;
+    if (lattice != MCLBM_D2Q9 && lattice != MCLBM_D3Q19) return fail(MCLBM_EINVAL, "bad lattice");
+    if (model < 0 || model > 2) return fail(MCLBM_EINVAL, "bad model");
+    return MCLBM_OK;
+}
+
+static double omega_interface(const mclbm_params *p)
+{
+    const double nuR = (p->tau_R - 0.5) / 3.0, nuB = (p->tau_B - 0.5) / 3.0;
+    const double nu = 1.0 / (0.5 / nuR + 0.5 / nuB);
+    return 2.0 / (6.0 * nu + 1.0);
+}
+
+mclbm_status mclbm_params_from_sigma(mclbm_params *p, double sigma)
+{
+    if (!p) return fail(MCLBM_EINVAL, "params is NULL");
+    if (p->model != MCLBM_CG) return fail(MCLBM_EINVAL, "sigma is set through A only for CG");
+    if (!(p->tau_R > 0.5) || !(p->tau_B > 0.5) || !(sigma >= 0.0)) return fail(MCLBM_EINVAL, "bad tau or sigma");
+    p->A = 9.0 * sigma * omega_interface(p) / 4.0;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_sigma_from_params(const mclbm_params *p, double *sigma)
+{
+    if (!p || !sigma) return fail(MCLBM_EINVAL, "NULL argument");
+    if (p->model != MCLBM_CG) return fail(MCLBM_EINVAL, "sigma follows from A only for CG");
+    if (!(p->tau_R > 0.5) || !(p->tau_B > 0.5)) return fail(MCLBM_EINVAL, "bad tau");
+    *sigma = 4.0 * p->A / (9.0 * omega_interface(p));
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_state_bytes(const mclbm_params *p, size_t *bytes)
+{
+    if (!bytes) return fail(MCLBM_EINVAL, "bytes is NULL");
+    mclbm_status s = validate(p);
+    if (s) return s;
+    *bytes = layout_of(*p).total;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_bytes_per_update(const mclbm_params *p, double *bytes)
+{
+    if (!bytes) return fail(MCLBM_EINVAL, "bytes is NULL");
+    mclbm_status s = validate(p);
+    if (s) return s;
+    *bytes = 2.0 * ncomp_of(p->model) * lattice_Q(p->lattice) * (double)storage_size(p->precision);
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_create(const mclbm_params *p, void *d_state, size_t bytes, void *stream, mclbm_sim **out)
+{
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    mclbm_status s = validate(p);
+    if (s) return s;
+    if (!d_state) return fail(MCLBM_EINVAL, "d_state is NULL");
+    if ((uintptr_t)d_state % 256) return fail(MCLBM_EINVAL, "d_state must be 256-byte aligned");
+    const Layout lay = layout_of(*p);
+    if (bytes < lay.total) return fail(MCLBM_ENOMEM, "state buffer has %zu bytes, needs %zu", bytes, lay.total);
+    mclbm_sim *sim = new (std::nothrow) mclbm_sim();
+    if (!sim) return fail(MCLBM_ENOMEM, "host allocation failed");
+    sim->prm = *p;
+    sim->kp = make_kparams(*p);
+    sim->ops = get_ops(p->lattice, p->precision, p->model, p->model == MCLBM_CG && p->Pi != 0.0);
+    sim->lay = lay;
+    sim->base = (char *)d_state;
+    sim->f[0] = sim->base;
+    sim->f[1] = sim->base + lay.fbytes;
+    sim->field = sim->base + lay.field_off;
+    sim->gfield = sim->base + lay.gfield_off;
+    sim->cur = 0;
+    sim->step = 0;
+    sim->stream = (hipStream_t)stream;
+    sim->fused = p->kernel != MCLBM_KERNEL_TWO_PASS && fused_ok(*p, sim->ops);
+    sim->in_batch = false;
+    hipError_t e = hipGetDevice(&sim->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&sim->d_flag, 256);
+    if (e == hipSuccess) e = hipMalloc((void **)&sim->d_partials, sizeof(double) * kNAcc * kRedBlocks);
+    if (e == hipSuccess) e = hipMalloc((void **)&sim->d_obs, sizeof(double) * kNAcc);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sim->h_obs, sizeof(double) * kNAcc, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sim->h_flag, sizeof(unsigned), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemsetAsync(sim->d_flag, 0, 256, sim->stream);
+    if (e != hipSuccess) {
+        mclbm_destroy(sim);
+        return fail(MCLBM_EDEVICE, "scratch allocation: %s", hipGetErrorString(e));
+    }
+    *out = sim;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_destroy(mclbm_sim *sim)
+{
+    if (!sim) return MCLBM_OK;
+    if (sim->stream || sim->d_flag) (void)hipStreamSynchronize(sim->stream);
+    if (sim->d_flag) (void)hipFree(sim->d_flag);
+    if (sim->d_partials) (void)hipFree(sim->d_partials);
+    if (sim->d_obs) (void)hipFree(sim->d_obs);
+    if (sim->h_obs) (void)hipHostFree(sim->h_obs);
+    if (sim->h_flag) (void)hipHostFree(sim->h_flag);
+    delete sim;
+    return MCLBM_OK;
+}
+
+static mclbm_status check_sim(mclbm_sim *sim)
+{
+    if (!sim) return fail(MCLBM_EINVAL, "sim is NULL");
+    if (sim->in_batch) return fail(MCLBM_EINVAL, "sim belongs to a live batch");
+    return MCLBM_OK;
+}
+
+static mclbm_status launched(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MCLBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_init_equilibrium(mclbm_sim *sim, const double *d_rhoR, const double *d_rhoB, const double *d_u)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!d_rhoR) return fail(MCLBM_EINVAL, "d_rhoR is NULL");
+    if (sim->prm.model != MCLBM_SC_MP && !d_rhoB) return fail(MCLBM_EINVAL, "d_rhoB is NULL");
+    sim->cur = 0;
+    sim->step = 0;
+    MCLBM_HIP(hipMemsetAsync(sim->d_flag, 0, sizeof(unsigned), sim->stream));
+    sim->ops->init(sim->kp, d_rhoR, sim->prm.model == MCLBM_SC_MP ? d_rhoR : d_rhoB, d_u, sim->f[0], sim->stream);
+    return launched("init");
+}
+
+mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged)
+{
+    if (!sim || !diverged) return fail(MCLBM_EINVAL, "NULL argument");
+    MCLBM_HIP(hipMemcpyAsync(sim->h_flag, sim->d_flag, sizeof(unsigned), hipMemcpyDeviceToHost, sim->stream));
+    MCLBM_HIP(hipStreamSynchronize(sim->stream));
+    *diverged = *sim->h_flag ? 1 : 0;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_step(mclbm_sim *sim, int64_t nsteps, int64_t check_every, int64_t *steps_done)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (nsteps < 0 || check_every < 0) return fail(MCLBM_EINVAL, "negative step count");
+    int64_t done = 0;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        sim->ops->step(sim->kp, sim->f[sim->cur], sim->f[sim->cur ^ 1], sim->field, sim->gfield, sim->d_flag,
+                       sim->fused, sim->stream);
+        sim->cur ^= 1;
+        ++sim->step;
+        ++done;
+        if (check_every > 0 && (done % check_every == 0 || t + 1 == nsteps)) {
+            s = launched("step");
+            if (s) { if (steps_done) *steps_done = done; return s; }
+            int32_t dv = 0;
+            s = mclbm_diverged(sim, &dv);
+            if (s) { if (steps_done) *steps_done = done; return s; }
+            if (dv) {
+                if (steps_done) *steps_done = done;
+                return MCLBM_DIVERGED;
+            }
+        }
+    }
+    if (steps_done) *steps_done = done;
+    return launched("step");
+}
+
+mclbm_status mclbm_moments(mclbm_sim *sim, double *d_rhoR, double *d_rhoB, double *d_u)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    sim->ops->density(sim->kp, sim->f[sim->cur], sim->field, sim->d_flag, sim->stream);
+    sim->ops->moments(sim->kp, sim->f[sim->cur], sim->field, d_rhoR, d_rhoB, d_u, sim->stream);
+    return launched("moments");
+}
+
+mclbm_status mclbm_observables(mclbm_sim *sim, mclbm_obs *out)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    const int nb = (int)std::min<long long>(kRedBlocks, grid_of(sim->kp.N));
+    sim->ops->density(sim->kp, sim->f[sim->cur], sim->field, sim->d_flag, sim->stream);
+    sim->ops->obs(sim->kp, sim->f[sim->cur], sim->field, eps_table(), sim->d_partials, nb, sim->stream);
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, sim->stream, sim->d_partials, nb, sim->d_obs);
+    s = launched("observables");
+    if (s) return s;
+    MCLBM_HIP(hipMemcpyAsync(sim->h_obs, sim->d_obs, sizeof(double) * kNAcc, hipMemcpyDeviceToHost, sim->stream));
+    MCLBM_HIP(hipStreamSynchronize(sim->stream));
+    const double *a = sim->h_obs;
+    memset(out, 0, sizeof *out);
+    out->mass_R = a[0];
+    out->mass_B = a[1];
+    out->mom[0] = a[2];
+    out->mom[1] = a[3];
+    out->mom[2] = a[4];
+    out->ekin = a[5];
+    out->umax = a[6];
+    out->red_volume = a[7];
+    out->diverged = a[8];
+    if (sim->prm.model == MCLBM_SC_MP) {
+        out->n_in = a[10];
+        out->n_out = a[12];
+        out->rho_in = a[10] > 0 ? a[9] / a[10] : 0.0;
+        out->rho_out = a[12] > 0 ? a[11] / a[12] : 0.0;
+    } else {
+        const EpsTable e = eps_table();
+        for (int m = 9; m >= 0; --m) {
+            const double *q = a + 9 + 4 * m;
+            if (q[1] > 0 && q[3] > 0) {
+                out->n_in = q[1];
+                out->n_out = q[3];
+                out->rho_in = q[0] / q[1];
+                out->rho_out = q[2] / q[3];
+                out->eps_used = e.e[m];
+                break;
+            }
+        }
+    }
+    out->step = sim->step;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_export_f(mclbm_sim *sim, double *d_f)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!d_f) return fail(MCLBM_EINVAL, "d_f is NULL");
+    sim->ops->export_f(sim->kp, sim->f[sim->cur], d_f, sim->stream);
+    return launched("export");
+}
+
+mclbm_status mclbm_import_f(mclbm_sim *sim, const double *d_f)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!d_f) return fail(MCLBM_EINVAL, "d_f is NULL");
+    MCLBM_HIP(hipMemsetAsync(sim->d_flag, 0, sizeof(unsigned), sim->stream));
+    sim->ops->import_f(sim->kp, d_f, sim->f[sim->cur], sim->stream);
+    return launched("import");
+}
+
+mclbm_status mclbm_checkpoint_bytes(const mclbm_sim *sim, size_t *bytes)
+{
+    if (!sim || !bytes) return fail(MCLBM_EINVAL, "NULL argument");
+    *bytes = (size_t)ncomp_of(sim->prm.model) * lattice_Q(sim->prm.lattice) * (size_t)sim->kp.N *
+             storage_size(sim->prm.precision);
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_checkpoint(mclbm_sim *sim, void *d_dst, int64_t *step)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!d_dst) return fail(MCLBM_EINVAL, "d_dst is NULL");
+    size_t b = 0;
+    mclbm_checkpoint_bytes(sim, &b);
+    MCLBM_HIP(hipMemcpyAsync(d_dst, sim->f[sim->cur], b, hipMemcpyDeviceToDevice, sim->stream));
+    if (step) *step = sim->step;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_restore(mclbm_sim *sim, const void *d_src, int64_t step)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!d_src || step < 0) return fail(MCLBM_EINVAL, "bad argument");
+    size_t b = 0;
+    mclbm_checkpoint_bytes(sim, &b);
+    MCLBM_HIP(hipMemcpyAsync(sim->f[sim->cur], d_src, b, hipMemcpyDeviceToDevice, sim->stream));
+    MCLBM_HIP(hipMemsetAsync(sim->d_flag, 0, sizeof(unsigned), sim->stream));
+    sim->step = step;
+    return MCLBM_OK;
+}
+
+// --------------------------------------------------------------------------
+// Batches.
+// --------------------------------------------------------------------------
+mclbm_status mclbm_batch_destroy(mclbm_batch *b)
+{
+    if (!b) return MCLBM_OK;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    for (mclbm_sim *s : b->sims) s->in_batch = false;
+    delete b;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t *target_steps, void *stream,
+                                mclbm_batch **out)
+{
+    if (!out || !sims || !target_steps || n <= 0) return fail(MCLBM_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!sims[i]) return fail(MCLBM_EINVAL, "sim %d is NULL", i);
+        if (sims[i]->in_batch) return fail(MCLBM_EINVAL, "sim %d is already in a batch", i);
+        if (target_steps[i] < 0) return fail(MCLBM_EINVAL, "negative target for sim %d", i);
+        for (int j = 0; j < i; ++j)
+            if (sims[j] == sims[i]) return fail(MCLBM_EINVAL, "sim %d appears twice", i);
+    }
+    mclbm_batch *b = new (std::nothrow) mclbm_batch();
+    if (!b) return fail(MCLBM_ENOMEM, "host allocation failed");
+    b->stream = (hipStream_t)stream;
+    b->sims.assign(sims, sims + n);
+    // group by (lattice, precision, model, repulsion), stable
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    std::vector<std::tuple<int, int, int, int>> keys;
+    for (int i = 0; i < n; ++i) {
+        const mclbm_params &p = sims[i]->prm;
+        auto key = std::make_tuple(p.lattice, p.precision, p.model, (int)(p.model == MCLBM_CG && p.Pi != 0.0));
+        if (!groups.count(key)) keys.push_back(key);
+        groups[key].push_back(i);
+    }
+    hipError_t e = hipMalloc((void **)&b->d_desc, sizeof(SimDesc) * n);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_desc, sizeof(SimDesc) * n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        mclbm_batch_destroy(b);
+        return fail(MCLBM_EDEVICE, "batch allocation: %s", hipGetErrorString(e));
+    }
+    int slot = 0;
+    for (auto &key : keys) {
+        mclbm_batch::Group g;
+        g.ops = sims[groups[key][0]]->ops;
+        g.first = slot;
+        g.count = (int)groups[key].size();
+        g.blocks = 0;
+        g.oblocks = 0;
+        g.any_outflow = false;
+        for (int idx : groups[key]) {
+            mclbm_sim *s = sims[idx];
+            (void)hipStreamSynchronize(s->stream);
+            SimDesc &d = b->h_desc[slot];
+            memset(&d, 0, sizeof d);
+            d.P = s->kp;
+            d.f[0] = s->f[0];
+            d.f[1] = s->f[1];
+            d.field = s->field;
+            d.gfield = s->gfield;
+            d.flag = s->d_flag;
+            d.block0 = g.blocks;
+            d.nblocks = grid_of(s->kp.N);
+            g.blocks += d.nblocks;
+            d.ocount = s->kp.has_outflow ? outflow_count(s->kp) : 0;
+            d.oblock0 = g.oblocks;
+            d.onblocks = grid_of(d.ocount);
+            g.oblocks += d.onblocks;
+            if (d.ocount) g.any_outflow = true;
+            d.steps = 0;
+            d.target = target_steps[idx];
+            d.cur = s->cur;
+            d.state = target_steps[idx] > 0 ? MCLBM_RUNNING : MCLBM_DONE;
+            b->order.push_back(idx);
+            b->step0.push_back(s->step);
+            ++slot;
+        }
+        b->groups.push_back(g);
+    }
+    for (int i = 0; i < n; ++i) {
+        e = hipMemsetAsync(sims[i]->d_flag, 0, sizeof(unsigned), b->stream);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(SimDesc) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        mclbm_batch_destroy(b);
+        return fail(MCLBM_EDEVICE, "batch upload: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < n; ++i) sims[i]->in_batch = true;
+    *out = b;
+    return MCLBM_OK;
+}
+
+static void batch_enqueue(mclbm_batch *b, int k)
+{
+    const int n = (int)b->sims.size();
+    for (int t = 0; t < k; ++t) {
+        for (const auto &g : b->groups)
+            g.ops->batch_step(b->d_desc + g.first, g.count, g.blocks, g.oblocks, g.any_outflow, b->stream);
+        hipLaunchKernelGGL(kb_advance, dim3((n + 63) / 64), dim3(64), 0, b->stream, b->d_desc, n);
+    }
+}
+
+mclbm_status mclbm_batch_step(mclbm_batch *b, int32_t ksteps, int32_t use_graph)
+{
+    if (!b || ksteps < 0) return fail(MCLBM_EINVAL, "bad batch step arguments");
+    if (ksteps == 0) return MCLBM_OK;
+    if (use_graph && !b->stream) return fail(MCLBM_EINVAL, "graph capture needs a non-null stream");
+    if (!use_graph) {
+        batch_enqueue(b, ksteps);
+        return launched("batch step");
+    }
+    if (!b->exec || b->graph_k != ksteps) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        MCLBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        batch_enqueue(b, ksteps);
+        hipError_t e = hipStreamEndCapture(b->stream, &b->graph);
+        if (e != hipSuccess) return fail(MCLBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        MCLBM_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_k = ksteps;
+    }
+    MCLBM_HIP(hipGraphLaunch(b->exec, b->stream));
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_batch_status(mclbm_batch *b, int32_t *status, int64_t *steps)
+{
+    if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+    const int n = (int)b->sims.size();
+    MCLBM_HIP(hipMemcpyAsync(b->h_desc, b->d_desc, sizeof(SimDesc) * n, hipMemcpyDeviceToHost, b->stream));
+    MCLBM_HIP(hipStreamSynchronize(b->stream));
+    for (int slot = 0; slot < n; ++slot) {
+        const int idx = b->order[slot];
+        const SimDesc &d = b->h_desc[slot];
+        mclbm_sim *s = b->sims[idx];
+        s->cur = d.cur;
+        s->step = b->step0[slot] + d.steps;
+        if (status) status[idx] = d.state;
+        if (steps) steps[idx] = d.steps;
+    }
+    return MCLBM_OK;
+}
+
+}  // extern "C"

@@ -90,13 +90,25 @@ def random_droplets(shape, count, rmin, rmax, seed, rho0_R=1.0, rho0_B=1.0, widt
                 break
         if ok:
             placed.append((c, r))
-    x, y, z = _grid(shape)
-    dmax = np.full(shape, -1e30)
+    # signed distance to the nearest sphere, evaluated only in a box around
+    # each sphere (beyond r + 12 width the profile is saturated to 1e-10)
+    dmax = np.full(shape, -12.0 * width)
     for (c, r) in placed:
-        dx = _min_image(x - c[0], nx, True)
-        dy = _min_image(y - c[1], ny, True)
-        dz = _min_image(z - c[2], nz, True)
-        np.maximum(dmax, r - np.sqrt(dx * dx + dy * dy + dz * dz), out=dmax)
+        reach = r + 12.0 * width
+        idx = []
+        for a, n in enumerate((nx, ny, nz)):
+            lo = int(np.floor(c[a] - reach))
+            q = np.arange(lo, int(np.ceil(c[a] + reach)) + 1)
+            if len(q) >= n:
+                q = np.arange(n)
+            idx.append(q)
+        qx, qy, qz = idx
+        dx = _min_image(qx % nx - c[0], nx, True)
+        dy = _min_image(qy % ny - c[1], ny, True)
+        dz = _min_image(qz % nz - c[2], nz, True)
+        d = r - np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
+        sub = np.ix_(qz % nz, qy % ny, qx % nx)
+        dmax[sub] = np.maximum(dmax[sub], d)
     rR, rB = fields_from_distance(dmax, rho0_R, rho0_B, width)
     return rR, rB, placed
 

@@ -1,0 +1,116 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/mclbm.h, and its host-side logic (defaults, validation,
+layout sizes, sigma <-> A of Eq. sigmaA) behaves as documented."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mclbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mclbm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2110_05197_amd as M
+    M.lib()
+    return M
+
+
+def test_library_exports_every_declared_function(M):
+    names = declared_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(M.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings(M):
+    assert M.version() == (1, 0)
+    L = M.lib()
+    for s in (0, 1, -1, -2, -3, -4):
+        assert L.mclbm_status_str(s)
+    assert L.mclbm_status_str(99) == b"unknown status"
+
+
+def test_defaults(M):
+    p = M.params_default(M.D3Q19, M.CG)
+    assert p["abi_version"] == 1 and p["beta"] == 0.7 and p["alpha_B"] == 0.2
+    assert (p["nx"], p["ny"], p["nz"]) == (64, 64, 64)
+    assert M.params_default(M.D2Q9, M.CG)["nz"] == 1
+
+
+def test_sigma_round_trip_eq_sigmaA(M):
+    """sigma = 4A/(9 omega_eff) with omega_eff = 2/(6 nu + 1) at rho^N = 0."""
+    p = M.make_params(lattice=M.D3Q19, tau_R=1.0, tau_B=0.55)
+    p = M.params_from_sigma(p, 0.05)
+    nuR, nuB = 0.5 / 3, 0.05 / 3
+    nu = 1 / (0.5 / nuR + 0.5 / nuB)
+    om = 2 / (6 * nu + 1)
+    assert math.isclose(p["A"], 9 * 0.05 * om / 4, rel_tol=1e-14)
+    assert math.isclose(M.sigma_from_params(p), 0.05, rel_tol=1e-14)
+    # equal taus: sigma = 4A/(9 omega) with omega = 1/tau
+    q = M.make_params(A=0.01, tau_R=1.0, tau_B=1.0)
+    assert math.isclose(M.sigma_from_params(q), 4 * 0.01 / 9, rel_tol=1e-14)
+
+
+@pytest.mark.parametrize("lattice,model,prec,expect", [
+    (1, 0, 1, 2 * 2 * 19 * 4),   # D3Q19 CG FP32: 304 B per update
+    (1, 0, 0, 2 * 2 * 19 * 8),
+    (1, 0, 3, 2 * 2 * 19 * 2),
+    (0, 0, 1, 2 * 2 * 9 * 4),
+    (1, 1, 1, 2 * 1 * 19 * 4),
+])
+def test_bytes_per_update(M, lattice, model, prec, expect):
+    p = M.make_params(lattice=lattice, model=model, precision=prec, nz=1 if lattice == 0 else 64)
+    assert M.bytes_per_update(p) == expect
+
+
+def test_state_bytes_layout(M):
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=32, ny=16, nz=8)
+    N = 32 * 16 * 8
+    f = 2 * 19 * N * 4
+    field = 3 * N * 4
+    align = lambda b: (b + 255) // 256 * 256
+    assert M.state_bytes(p) == 2 * align(f) + align(field)
+    p_rep = dict(p, Pi=0.01)
+    assert M.state_bytes(p_rep) == 2 * align(f) + align(field) + align(3 * N * 4)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau_R=0.5), dict(tau_B=0.4), dict(beta=1.5), dict(rho0_B=2.0), dict(alpha_B=1.0),
+    dict(nx=1), dict(nz=1), dict(bc=(0, 3, 0)), dict(precision=7), dict(abi_version=9),
+    dict(kernel=5), dict(A=-1.0),
+])
+def test_validation_rejects(M, bad):
+    p = M.make_params(lattice=M.D3Q19, **bad)
+    with pytest.raises(M.MclbmError) as e:
+        M.state_bytes(p)
+    assert e.value.status == -1
+
+
+def test_unsupported_combinations(M):
+    with pytest.raises(M.MclbmError) as e:
+        M.state_bytes(M.make_params(lattice=M.D3Q19, model=M.SC_MP, Pi=0.01))
+    assert e.value.status == -2
+    # fused needs D3Q19, no repulsion, nx % 32 == 0, FP32-family storage
+    with pytest.raises(M.MclbmError) as e:
+        M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, kernel=M.KERNEL_FUSED))
+    assert e.value.status == -2
+    with pytest.raises(M.MclbmError):
+        M.state_bytes(M.make_params(lattice=M.D3Q19, nx=40, kernel=M.KERNEL_FUSED))
+    with pytest.raises(M.MclbmError):
+        M.state_bytes(M.make_params(lattice=M.D3Q19, precision=M.FP64, kernel=M.KERNEL_FUSED))
+    assert M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=32, kernel=M.KERNEL_FUSED)) > 0
+
+
+def test_d2q9_rejects_z_boundaries(M):
+    with pytest.raises(M.MclbmError):
+        M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, bc=(0, 0, 1)))

@@ -1,0 +1,89 @@
+"""Parity at the benchmark's full size and launch configuration: D3Q19 CG,
+FP32, fused kernel, 256^3 with the 32-droplet fields.
+
+A node's populations after one step depend only on the populations within
+Chebyshev distance 2 (streaming pulls from distance 1, whose collision reads
+densities and colour field at distance 1 again), so the oracle recomputes
+sampled nodes exactly from their 5x5x5 neighbourhoods (a periodic 5^3 box
+whose wrap-around never reaches the centre's dependencies).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_05197_amd as M
+    M.lib()
+    return M
+
+
+def test_fullsize_sampled_nodes_match_oracle(M, orc):
+    import torch
+    sys.path.insert(0, ".")
+    import bench
+    n = 256
+    rR, rB = bench.workload_fields(n)
+    p = bench.params(n, precision=M.FP32, kernel=M.KERNEL_FUSED)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB)
+    sim.step(5)                         # leave the initial equilibrium
+    f0 = sim.export_f()
+    st, _ = sim.step(1)
+    assert st == M.OK
+    f1 = sim.export_f()
+    rng = np.random.default_rng(5)
+    # half the samples on interfaces (|rho^N| < 0.9), half anywhere
+    rho = f0.sum(dim=1)
+    rn = ((rho[0] - rho[1]) / (rho[0] + rho[1])).cpu().numpy()
+    iface = np.argwhere(np.abs(rn) < 0.9)
+    pts = [tuple(iface[i]) for i in rng.choice(len(iface), 24, replace=False)]
+    pts += [tuple(rng.integers(0, n, 3)) for _ in range(8)]
+    po = dict(p, nx=5, ny=5, nz=5)
+    worst = 0.0
+    scale = float(f1.abs().max())
+    for (z, y, x) in pts:
+        iz = [(z + d) % n for d in range(-2, 3)]
+        iy = [(y + d) % n for d in range(-2, 3)]
+        ix = [(x + d) % n for d in range(-2, 3)]
+        box = f0[:, :, iz][:, :, :, iy][:, :, :, :, ix].cpu().numpy()
+        out = orc.run(po, box, 1)
+        e = float(np.abs(out[:, :, 2, 2, 2] - f1[:, :, z, y, x].cpu().numpy()).max()) / scale
+        worst = max(worst, e)
+    say(f"[fullsize] 256^3 fused FP32: worst sampled rel err after 1 step {worst:.2e}")
+    assert worst <= 2e-6
+    del f0, f1
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_invariants_over_bench_steps(M):
+    import sys as _s
+    _s.path.insert(0, ".")
+    import bench
+    n = 256
+    rR, rB = bench.workload_fields(n)
+    p = bench.params(n, precision=M.FP32)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB)
+    o0 = sim.observables()
+    st, done = sim.step(220, check_every=110)
+    assert st == M.OK and done == 220
+    o1 = sim.observables()
+    dR = abs(o1["mass_R"] - o0["mass_R"]) / o0["mass_R"]
+    dB = abs(o1["mass_B"] - o0["mass_B"]) / o0["mass_B"]
+    say(f"[fullsize] mass drift R {dR:.2e} B {dB:.2e}, |mom| {abs(o1['mom_x']):.2e}, "
+        f"umax {o1['umax']:.2e}")
+    assert dR < 1e-5 and dB < 1e-6
+    assert o1["umax"] < 0.05
+    assert abs(o1["mom_x"]) + abs(o1["mom_y"]) + abs(o1["mom_z"]) < 1e-6 * o0["mass_B"]

@@ -1,0 +1,386 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, element by element.
+
+Tolerances: relative max-norm error max|f_gpu - f_oracle| / max|f_oracle|
+(and the same on rho_k) <= 1e-10 for the FP64 path and <= 2e-5 for FP32
+after 100 steps.  FP16 storage and the mixed path report their error.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2110_05197_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_05197_amd as M
+    M.lib()
+    return M
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def gpu_run(M, p, rR, rB, u, steps, kernel=None):
+    q = dict(p)
+    if kernel is not None:
+        q["kernel"] = kernel
+    sim = M.Sim(q)
+    sim.init_equilibrium(rR, rB, u)
+    st, done = sim.step(steps, check_every=steps if steps else 0)
+    assert st == M.OK and done == steps
+    f = sim.export_f().cpu().numpy()
+    return sim, f
+
+
+def compare(M, orc, p, rR, rB, u, steps, tol, kernel=None, label=""):
+    say(f"[parity] {label} shape={(p['nz'], p['ny'], p['nx'])} lattice={p['lattice']} "
+        f"model={p['model']} prec={p['precision']} kernel={kernel} steps={steps}")
+    fo = orc.run(p, orc.init_equilibrium(p, rR, rB, u), steps)
+    sim, fg = gpu_run(M, p, rR, rB, u, steps, kernel)
+    e_f = rel_err(fg, fo)
+    ro = fo.sum(axis=1)
+    rg = fg.sum(axis=1)
+    e_r = rel_err(rg, ro)
+    say(f"    rel max err f={e_f:.3e} rho={e_r:.3e} (tol {tol:g})")
+    assert e_f <= tol and e_r <= tol
+    return sim, fg, fo
+
+
+def cg_droplet_case(shape, seed, gamma=1.0, lattice=1, **kw):
+    rho0_B = 1.0 / gamma
+    R = min(s for s in shape if s > 1) / 4.0
+    rR, rB = inputs.droplet(shape, R, 1.0, rho0_B)
+    rR = rR * (1 + inputs.noise(shape, 0.01, seed))
+    rB = rB * (1 + inputs.noise(shape, 0.01, seed + 1))
+    u = np.zeros((3,) + shape)
+    for a in range(2 if lattice == 0 else 3):
+        u[a] = inputs.noise(shape, 0.02, seed + 2 + a)
+    return rR, rB, u
+
+
+# --------------------------------------------------------------------------
+# Colour gradient
+# --------------------------------------------------------------------------
+def test_cg_d2q9_fp64_static_droplet(M, orc):
+    """64x64 D2Q9 droplet R = 16, A = 0.01, tau = 1, beta = 0.7, FP64."""
+    p = M.make_params(lattice=M.D2Q9, model=M.CG, precision=M.FP64, nx=64, ny=64, nz=1, A=0.01)
+    rR, rB = inputs.droplet((1, 64, 64), 16.0)
+    compare(M, orc, p, rR, rB, None, 100, 1e-10, label="cg-d2q9-config1")
+
+
+def test_cg_d2q9_fp64_ragged_moving(M, orc):
+    shape = (1, 45, 70)
+    p = M.make_params(lattice=M.D2Q9, precision=M.FP64, nx=70, ny=45, nz=1, A=0.03, tau_R=0.7,
+                      tau_B=1.2, rho0_B=0.1)
+    rR, rB, u = cg_droplet_case(shape, 11, gamma=10.0, lattice=0)
+    compare(M, orc, p, rR, rB, u, 100, 1e-10, label="cg-d2q9-ragged")
+
+
+def test_cg_d3q19_fp64_ragged_density_ratio(M, orc):
+    shape = (30, 36, 40)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP64, nx=40, ny=36, nz=30, A=0.02, tau_R=0.7,
+                      tau_B=1.1, rho0_B=0.1)
+    rR, rB, u = cg_droplet_case(shape, 12, gamma=10.0)
+    compare(M, orc, p, rR, rB, u, 100, 1e-10, label="cg-d3q19-fp64")
+
+
+def test_cg_d3q19_fp64_plain_equilibrium(M, orc):
+    shape = (16, 20, 24)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP64, nx=24, ny=20, nz=16, A=0.02,
+                      enhanced_eq=0, rho0_B=0.5)
+    rR, rB, u = cg_droplet_case(shape, 13, gamma=2.0)
+    compare(M, orc, p, rR, rB, u, 100, 1e-10, label="cg-d3q19-plain-eq")
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_cg_d3q19_fp32(M, orc, kernel):
+    shape = (24, 32, 64)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=64, ny=32, nz=24, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 14)
+    compare(M, orc, p, rR, rB, u, 100, 2e-5, kernel=kernel, label="cg-d3q19-fp32")
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_cg_d3q19_fp32_density_ratio_tile_shapes(M, orc, kernel):
+    # nx = 96: the fused kernel uses 32-wide tiles; ny = 20: 4-row tiles
+    shape = (18, 20, 96)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=96, ny=20, nz=18, A=0.02,
+                      rho0_B=0.1, tau_R=0.8, tau_B=1.0)
+    rR, rB, u = cg_droplet_case(shape, 15, gamma=10.0)
+    compare(M, orc, p, rR, rB, u, 100, 2e-5, kernel=kernel, label="cg-d3q19-fp32-gamma10")
+
+
+@pytest.mark.parametrize("prec,tol", [(3, 5e-3), (2, 2e-5)])
+def test_cg_d3q19_fp16_and_mixed_error(M, orc, prec, tol):
+    shape = (16, 16, 32)
+    p = M.make_params(lattice=M.D3Q19, precision=prec, nx=32, ny=16, nz=16, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 16)
+    compare(M, orc, p, rR, rB, u, 100, tol, label=f"cg-d3q19-prec{prec}")
+
+
+def test_mixed_beats_fp32_at_density_ratio_1000(M, orc):
+    """gamma = 1000 (rho_R^0 = 1000, rho_B^0 = 1, so that the ambient pressure
+    rho_B c_sB^2 = 0.4 dwarfs the Laplace pressure): the mixed path's error
+    against the oracle in the light phase's density is no worse than plain
+    FP32 shifted storage, and both stay within the FP32 tolerance."""
+    shape = (16, 16, 32)
+    res = {}
+    for prec in (1, 2):
+        p = M.make_params(lattice=M.D3Q19, precision=prec, nx=32, ny=16, nz=16, A=0.01,
+                          rho0_R=1000.0, rho0_B=1.0, tau_R=1.0, tau_B=0.55)
+        rR, rB = inputs.ligament(shape, 4.0, 20.0, 1000.0, 1.0, axis=0)
+        say(f"[parity] gamma=1000 prec={prec}")
+        fo = orc.run(p, orc.init_equilibrium(p, rR, rB, None), 100)
+        assert orc.observables(p, fo)["diverged"] == 0
+        _, fg = gpu_run(M, p, rR, rB, None, 100)
+        eB = float(np.abs(fg[1].sum(axis=0) - fo[1].sum(axis=0)).max())
+        res[prec] = (rel_err(fg, fo), eB)
+        say(f"    prec={prec} rel err f={res[prec][0]:.3e} light-phase rho abs err={eB:.3e}")
+    assert res[1][0] <= 2e-5 and res[2][0] <= 2e-5
+    assert res[2][1] <= res[1][1] * 1.01
+
+
+# --------------------------------------------------------------------------
+# Boundaries (walls on x/y, outflow on z)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,kernel,tol", [(0, 1, 1e-10), (1, 1, 2e-5), (1, 2, 2e-5)])
+def test_cg_walls_outflow(M, orc, prec, kernel, tol):
+    shape = (40, 16, 32)
+    p = M.make_params(lattice=M.D3Q19, precision=prec, nx=32, ny=16, nz=40, bc=(1, 1, 2),
+                      A=0.02, rho0_B=0.1, tau_R=1.0, tau_B=0.6)
+    rR, rB = inputs.ligament(shape, 5.0, 30.0, 1.0, 0.1, axis=2)
+    u = np.zeros((3,) + shape)
+    u[2] = 0.01
+    compare(M, orc, p, rR, rB, u, 100, tol, kernel=kernel, label="cg-walls-outflow")
+
+
+def test_cg_d2q9_walls(M, orc):
+    shape = (1, 30, 50)
+    p = M.make_params(lattice=M.D2Q9, precision=M.FP64, nx=50, ny=30, nz=1, bc=(2, 1, 0), A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 17, lattice=0)
+    compare(M, orc, p, rR, rB, u, 100, 1e-10, label="cg-d2q9-walls")
+
+
+# --------------------------------------------------------------------------
+# Shan-Chen variants and the repulsion force
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("lattice,prec,kernel,tol", [(1, 0, 1, 1e-10), (1, 1, 1, 2e-5), (1, 1, 2, 2e-5),
+                                                     (0, 0, 1, 1e-10)])
+def test_sc_multiphase(M, orc, lattice, prec, kernel, tol):
+    shape = (16, 16, 32) if lattice == 1 else (1, 40, 48)
+    p = M.make_params(lattice=lattice, model=M.SC_MP, precision=prec, nx=shape[2], ny=shape[1],
+                      nz=shape[0], G=-5.0, tau_R=0.9, rho0_R=1.9, rho0_B=0.12)
+    rR, rB = inputs.droplet(shape, 6.0, 1.9, 0.12)
+    rho = rR + rB + inputs.noise(shape, 0.01, 18)
+    compare(M, orc, p, rho, None, None, 100, tol, kernel=kernel, label="sc-mp")
+
+
+@pytest.mark.parametrize("lattice,prec,kernel,tol", [(1, 0, 1, 1e-10), (1, 1, 2, 2e-5), (0, 0, 1, 1e-10)])
+def test_sc_two_component(M, orc, lattice, prec, kernel, tol):
+    shape = (16, 16, 32) if lattice == 1 else (1, 40, 48)
+    p = M.make_params(lattice=lattice, model=M.SC_MC, precision=prec, nx=shape[2], ny=shape[1],
+                      nz=shape[0], G_RB=1.2, tau_R=1.0, tau_B=0.8, rho0_R=1.0, rho0_B=1.0)
+    rR, rB = inputs.droplet(shape, 6.0, 1.0, 1.0)
+    compare(M, orc, p, rR + 0.04, rB + 0.04, None, 100, tol, kernel=kernel, label="sc-mc")
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_cg_repulsion(M, orc, lattice):
+    shape = (1, 32, 48) if lattice == 0 else (12, 16, 32)
+    nx = shape[2]
+    x = np.arange(nx, dtype=float)
+    films = (nx / 4 - 0.5, 3 * nx / 4 - 0.5)
+    dist = np.min([np.abs(x - c - nx * np.round((x - c) / nx)) for c in films], axis=0)
+    phi = np.broadcast_to(np.tanh((dist - 2.5) / 2.0), shape)
+    rR = 0.5 * (1 + phi) * (1 + inputs.noise(shape, 0.01, 19))
+    rB = 0.5 * (1 - phi)
+    p = M.make_params(lattice=lattice, precision=M.FP64, nx=nx, ny=shape[1], nz=shape[0],
+                      A=0.02, Pi=0.01, chi=1.0)
+    compare(M, orc, p, rR, rB, None, 100, 1e-10, label="cg-repulsion")
+
+
+# --------------------------------------------------------------------------
+# Moments, observables, invariants of the GPU path itself
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_moments_and_observables_fp64(M, orc, model):
+    shape = (12, 16, 20)
+    kw = dict(G=-5.0, rho0_R=1.9, rho0_B=0.12) if model == 1 else dict(G_RB=1.2, A=0.02)
+    p = M.make_params(lattice=M.D3Q19, model=model, precision=M.FP64, nx=20, ny=16, nz=12, **kw)
+    if model == 1:
+        rR, rB = inputs.droplet(shape, 4.0, 1.9, 0.12)
+        rR, rB = rR + rB, None
+    else:
+        rR, rB = inputs.droplet(shape, 4.0)
+        rR, rB = rR + 0.02, rB + 0.02
+    say(f"[parity] moments/observables model={model}")
+    fo = orc.run(p, orc.init_equilibrium(p, rR, rB, None), 30)
+    sim, fg = gpu_run(M, p, rR, rB, None, 30)
+    oo = orc.observables(p, fo)
+    og = sim.observables()
+    for k in ("mass_R", "mass_B", "mom_x", "mom_y", "mom_z", "ekin", "umax", "rho_in", "rho_out",
+              "red_volume", "n_in", "n_out", "eps_used", "diverged"):
+        scale = max(abs(oo[k]), 1e-300)
+        if k.startswith("mom"):
+            scale = max(scale, oo["mass_R"])
+        assert abs(og[k] - oo[k]) <= 1e-10 * scale, (k, og[k], oo[k])
+    rRg, rBg, ug = [t.cpu().numpy() for t in sim.moments()]
+    rRo, rBo, jo = orc.moments(p, fo)
+    assert rel_err(rRg, rRo) < 1e-12
+    if model != 1:
+        assert rel_err(rBg, rBo) < 1e-12
+    if model == 0:   # bare velocity for CG
+        uo = jo / (rRo + rBo)
+        assert np.abs(ug - uo).max() < 1e-12
+
+
+def test_fp32_mass_conservation(M):
+    shape = (32, 32, 64)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=64, ny=32, nz=32, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 20)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB, u)
+    o0 = sim.observables()
+    sim.step(500)
+    o1 = sim.observables()
+    say(f"[fp32 mass] drift R {abs(o1['mass_R'] - o0['mass_R']) / o0['mass_R']:.2e} "
+        f"B {abs(o1['mass_B'] - o0['mass_B']) / o0['mass_B']:.2e}")
+    # FP32 rounding at interface nodes: about 1e-7 of the colour mass per step
+    assert abs(o1["mass_R"] - o0["mass_R"]) / o0["mass_R"] < 500 * 2e-7
+    assert abs(o1["mass_B"] - o0["mass_B"]) / o0["mass_B"] < 500 * 2e-7
+
+
+def test_fused_equals_two_pass_bitwise(M):
+    for bc in ((0, 0, 0), (1, 1, 2)):
+        for model in (0, 1, 2):
+            shape = (20, 16, 64)
+            kw = dict(G=-5.0, rho0_R=1.9, rho0_B=0.12) if model == 1 else dict(G_RB=1.2, A=0.02)
+            p = M.make_params(lattice=M.D3Q19, model=model, precision=M.FP32, nx=64, ny=16, nz=20,
+                              bc=bc, **kw)
+            if model == 1:
+                a, b = inputs.droplet(shape, 5.0, 1.9, 0.12)
+                rR, rB = a + b, None
+            else:
+                rR, rB, _ = cg_droplet_case(shape, 21)
+            say(f"[bitwise] fused vs two-pass bc={bc} model={model}")
+            _, f1 = gpu_run(M, p, rR, rB, None, 37, kernel=1)
+            _, f2 = gpu_run(M, p, rR, rB, None, 37, kernel=2)
+            assert np.array_equal(f1, f2)
+
+
+def test_checkpoint_restore_bitwise(M):
+    shape = (16, 16, 32)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=32, ny=16, nz=16, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 22)
+    a = M.Sim(p)
+    a.init_equilibrium(rR, rB, u)
+    a.step(40)
+    buf, st = a.checkpoint()
+    a.step(40)
+    fa = a.export_f().cpu().numpy()
+    b = M.Sim(p)
+    b.init_equilibrium(rR, rB, u)
+    b.restore(buf, st)
+    b.step(40)
+    assert b.observables()["step"] == 80
+    assert np.array_equal(b.export_f().cpu().numpy(), fa)
+
+
+def test_divergence_is_detected(M):
+    shape = (8, 8, 32)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=32, ny=8, nz=8, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 23)
+    s = M.Sim(p)
+    s.init_equilibrium(rR, rB, u)
+    f = s.export_f()
+    f[0, 3, 2, 2, 2] = float("nan")
+    s.import_f(f)
+    st, done = s.step(50, check_every=10)
+    assert st == M.DIVERGED and done == 10
+    assert s.observables()["diverged"] == 1.0
+
+
+def test_import_export_round_trip(M):
+    shape = (8, 8, 32)
+    for prec in (0, 1):
+        p = M.make_params(lattice=M.D3Q19, precision=prec, nx=32, ny=8, nz=8)
+        rR, rB, u = cg_droplet_case(shape, 24)
+        s = M.Sim(p)
+        s.init_equilibrium(rR, rB, u)
+        f = s.export_f()
+        s.import_f(f)
+        assert (s.export_f() == f).all()
+
+
+# --------------------------------------------------------------------------
+# Batched stepping: bitwise the same as solo, with and without graphs
+# --------------------------------------------------------------------------
+def test_batch_invariance_bitwise(M):
+    cases = [
+        (M.make_params(lattice=M.D2Q9, precision=M.FP32, nx=48, ny=40, nz=1, A=0.02), (1, 40, 48), 30),
+        (M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=24, ny=20, nz=16, A=0.01), (16, 20, 24), 45),
+        (M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=32, ny=16, nz=16, A=0.03, rho0_B=0.1),
+         (16, 16, 32), 20),
+        (M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=M.FP32, nx=16, ny=16, nz=16, G_RB=1.2),
+         (16, 16, 16), 33),
+        (M.make_params(lattice=M.D3Q19, precision=M.FP64, nx=20, ny=12, nz=10, A=0.02, bc=(1, 0, 2)),
+         (10, 12, 20), 25),
+    ]
+    inits = []
+    for i, (p, shape, _) in enumerate(cases):
+        lat = p["lattice"]
+        rR, rB, u = cg_droplet_case(shape, 30 + i, gamma=p["rho0_R"] / p["rho0_B"], lattice=lat)
+        inits.append((rR, rB, u))
+    solo = []
+    for (p, shape, n), (rR, rB, u) in zip(cases, inits):
+        _, f = gpu_run(M, p, rR, rB, u, n, kernel=1)
+        solo.append(f)
+    for use_graph in (False, True):
+        say(f"[batch] use_graph={use_graph}")
+        sims = []
+        for (p, shape, n), (rR, rB, u) in zip(cases, inits):
+            s = M.Sim(dict(p, kernel=1))
+            s.init_equilibrium(rR, rB, u)
+            sims.append(s)
+        b = M.Batch(sims, [n for (_, _, n) in cases])
+        for _ in range(10):
+            b.step(7, use_graph=use_graph)
+        st, steps = b.status()
+        assert st == [M.DONE] * len(cases)
+        assert steps == [n for (_, _, n) in cases]
+        b.close()
+        for s, f in zip(sims, solo):
+            assert np.array_equal(s.export_f().cpu().numpy(), f)
+
+
+def test_batch_stops_diverged_member(M):
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=16, ny=16, nz=16, A=0.02)
+    shape = (16, 16, 16)
+    rR, rB, u = cg_droplet_case(shape, 40)
+    good, bad = M.Sim(p), M.Sim(p)
+    good.init_equilibrium(rR, rB, u)
+    bad.init_equilibrium(rR, rB, u)
+    f = bad.export_f()
+    f[1, 0, 3, 3, 3] = float("inf")
+    bad.import_f(f)
+    b = M.Batch([good, bad], [30, 30])
+    b.step(10)
+    b.step(10)
+    b.step(10)
+    st, steps = b.status()
+    assert st == [M.DONE, M.STOPPED_DIVERGED]
+    assert steps[0] == 30 and steps[1] == 1
