@@ -91,6 +91,37 @@ def cpu_baseline(rR, rB, n: int, steps: int):
                        f"({dt:.1f} s wall)")
 
 
+def serving_leg(full: bool):
+    """Sweep serving: continuous batching (FP32 / mixed, batched graphs) against
+    one-at-a-time FP64 solves of the same seeded trace on the same GPU."""
+    from paper_2110_05197_amd import serve
+    if full:
+        kw = dict(n=256)
+        desc = ("256 requests, Poisson 20/s, CG/SC droplet/ligament, D2Q9 64^2-512^2 / D3Q19 "
+                "64^3-160^3, gamma 10^U(0,3), nu ratio 10^U(0,2), sigma 10^U(-3,-1), 1000-20000 steps")
+    else:
+        kw = dict(n=64, rate=200.0, d2_sizes=(64, 96, 128, 192, 256), d3_sizes=(32, 48, 64, 80, 96),
+                  steps_range=(500, 4000))
+        desc = ("reduced trace: 64 requests, Poisson 200/s (saturating), CG/SC droplet/ligament, "
+                "D2Q9 64^2-256^2 / D3Q19 32^3-96^3, gamma 10^U(0,3), nu ratio 10^U(0,2), "
+                "sigma 10^U(-3,-1), 500-4000 steps")
+    print(f"[bench] serving: {desc}", file=sys.stderr, flush=True)
+    trace = serve.make_trace(seed=0, **kw)
+    server = serve.Server(k_steps=100)
+    done, wall = server.run(trace)
+    batched = serve.summarize(done, wall)
+    print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+    trace2 = serve.make_trace(seed=0, **kw)
+    done2, wall2 = serve.serve_one_at_a_time(trace2)
+    fifo = serve.summarize(done2, wall2)
+    print(f"[bench] one-at-a-time FP64: {fifo}", file=sys.stderr, flush=True)
+    agree = sum(1 for a, b in zip(sorted(done, key=lambda r: r.rid), sorted(done2, key=lambda r: r.rid))
+                if a.outcome == b.outcome)
+    return dict(trace=desc, batched=batched, one_at_a_time_fp64=fifo,
+                speedup_throughput=round(batched["throughput_req_s"] / fifo["throughput_req_s"], 3),
+                outcome_agreement=f"{agree}/{len(done)}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,8 +130,11 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", type=int, default=1, help="0 FP64, 1 FP32, 2 mixed, 3 FP16")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto (fused), 1 two-pass, 2 fused")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the sweep-serving leg")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serve the full 256-request trace (minutes) instead of the reduced one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -149,6 +183,10 @@ def main():
         print(f"[bench] cpu baseline ({args.cpu_steps} oracle steps)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(rR, rB, n, args.cpu_steps)
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_leg(args.serve_full)
+
     dtype = {0: "f64", 1: "f32", 2: "f32+f64", 3: "f16-storage/f32"}[args.precision]
     out = {
         "metric": METRIC,
@@ -181,6 +219,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "mass_drift": drift,
+        "serving": serving,
     }
     print(json.dumps(out))
 

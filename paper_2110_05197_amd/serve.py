@@ -1,0 +1,272 @@
+"""Continuous-batching sweep serving over the mclbm batch API.
+
+Requests are independent simulations (colour gradient or Shan-Chen, D2Q9 or
+D3Q19, droplet or ligament, a density ratio, viscosity ratio and surface
+tension) that arrive over time, as the parameter sweeps of the paper's
+Laplace, stability and dynamics studies do.  The server keeps every admitted
+simulation resident in HBM, admits arrivals as soon as memory allows, and
+advances all resident simulations together: one batched launch per kernel
+per group of equal (lattice, model, precision), captured as a HIP graph of K
+steps and replayed.  Between replays it polls the per-simulation status
+words, retires simulations that are done or diverged (NaN, Inf or rho <= 0)
+and admits waiting ones.
+
+The reference point is the same trace served one at a time in arrival order,
+in FP64, with one simulation's two-pass kernels per launch and no graphs.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the trace starts
+    params: dict            # mclbm_params fields
+    case: str               # "droplet" or "ligament"
+    steps: int
+    gamma: float
+    nu_ratio: float
+    sigma: float
+    # filled in by the server
+    admitted: float = math.nan
+    finished: float = math.nan
+    outcome: str = ""
+    steps_done: int = 0
+    info: dict = field(default_factory=dict)
+
+
+def sc_coexistence_ratio(G: float) -> float:
+    """Liquid/gas density ratio of the Shan-Chen multiphase model (psi = 1 -
+    exp(-rho)) under Guo forcing, from p(l) = p(g) and the integral of
+    (p - p0) psi'/psi over [g, l] being zero; nan below the critical |G| = 4."""
+    if G >= -4.0:
+        return float("nan")
+    from scipy.integrate import quad
+    from scipy.optimize import fsolve
+    psi = lambda r: 1 - np.exp(-r)
+    dpsi = lambda r: np.exp(-r)
+    pr = lambda r: r / 3 + G * psi(r) ** 2 / 6
+
+    def eqs(v):
+        l, g = np.exp(v)
+        return [pr(l) - pr(g), quad(lambda r: (pr(r) - pr(l)) * dpsi(r) / psi(r), g, l, limit=200)[0]]
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        sol = fsolve(eqs, [np.log(2.0), np.log(0.1)], full_output=True)
+    l, g = np.exp(sol[0])
+    return float(l / g) if sol[2] == 1 else float("nan")
+
+
+_SC_TABLE = None
+
+
+def sc_coupling_for_ratio(gamma: float) -> float:
+    """G whose Shan-Chen coexistence has liquid/gas ratio gamma, interpolated
+    in log(ratio) on a table of the closed form over G in [-4.1, -8];
+    ratios beyond the table clamp to its strongest coupling."""
+    global _SC_TABLE
+    if _SC_TABLE is None:
+        Gs = np.linspace(-4.1, -8.0, 24)
+        rs = np.array([sc_coexistence_ratio(g) for g in Gs])
+        ok = np.isfinite(rs) & (rs > 1)
+        Gs, rs = Gs[ok], rs[ok]
+        order = np.argsort(rs)
+        _SC_TABLE = (np.log(rs[order]), Gs[order])
+    lr, Gs = _SC_TABLE
+    return float(np.interp(np.log(gamma), lr, Gs))
+
+
+def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 512),
+               d3_sizes=(64, 80, 96, 112, 128, 144, 160), steps_range=(1000, 20000),
+               precisions=(1, 2)):
+    """Seeded request trace: Poisson arrivals at `rate` per second; model CG
+    or SC (p = 1/2); droplet (R = L/4) or ligament (R = L/8, aspect 5, capped
+    to 0.8 L); D2Q9 or D3Q19 (p = 1/2) with L from the size lists; density
+    ratio 10^U(0,3), viscosity ratio 10^U(0,2), sigma 10^U(-3,-1); steps
+    U{steps_range}; FP32 or mixed storage."""
+    import paper_2110_05197_amd as M
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n):
+        t += rng.exponential(1.0 / rate)
+        model = "CG" if rng.random() < 0.5 else "SC"
+        case = "droplet" if rng.random() < 0.5 else "ligament"
+        d3 = rng.random() < 0.5
+        L = int(rng.choice(d3_sizes if d3 else d2_sizes))
+        gamma = 10 ** rng.uniform(0, 3)
+        nu_ratio = 10 ** rng.uniform(0, 2)
+        sigma = 10 ** rng.uniform(-3, -1)
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        prec = int(rng.choice(precisions))
+        lattice = M.D3Q19 if d3 else M.D2Q9
+        base = dict(lattice=lattice, nx=L, ny=L, nz=L if d3 else 1, precision=prec,
+                    kernel=M.KERNEL_TWO_PASS)
+        # heavy fluid more viscous: nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)
+        nu0 = 1.0 / 6.0
+        nuR, nuB = nu0 * math.sqrt(nu_ratio), nu0 / math.sqrt(nu_ratio)
+        if model == "CG":
+            p = M.make_params(model=M.CG, rho0_R=gamma, rho0_B=1.0, tau_R=0.5 + 3 * nuR,
+                              tau_B=0.5 + 3 * nuB, **base)
+            p = M.params_from_sigma(p, sigma)
+        else:
+            G = sc_coupling_for_ratio(gamma) if gamma > 1.5 else -4.5
+            p = M.make_params(model=M.SC_MP, G=G, tau_R=1.0, rho0_R=2.0, rho0_B=0.2, **base)
+        out.append(Request(rid, t, p, case, steps, gamma, nu_ratio, sigma))
+    return out
+
+
+def initial_fields(req: Request):
+    """Droplet or ligament fields for a request (inputs recipe)."""
+    p = req.params
+    shape = (p["nz"], p["ny"], p["nx"])
+    L = p["nx"]
+    if p["model"] == 1:
+        # SC multiphase: liquid droplet at ~2 in vapour ~0.2 (it relaxes to its coexistence)
+        rhoL, rhoG = 2.0, 0.2
+    else:
+        rhoL, rhoG = p["rho0_R"], p["rho0_B"]
+    if req.case == "droplet":
+        rR, rB = inputs.droplet(shape, L / 4.0, rhoL, rhoG)
+    else:
+        R = L / 8.0
+        rR, rB = inputs.ligament(shape, R, min(10 * R, 0.8 * L), rhoL, rhoG, axis=0)
+    if p["model"] == 1:
+        return rR + rB, None
+    return rR, rB
+
+
+def footprint(req: Request) -> int:
+    import paper_2110_05197_amd as M
+    return M.state_bytes(req.params)
+
+
+class Server:
+    """Continuous batching: admit by free HBM, step resident sims together."""
+
+    def __init__(self, k_steps=100, use_graph=True, reserve_bytes=4 << 30, max_resident=512,
+                 log=None):
+        import torch
+        self.k = k_steps
+        self.use_graph = use_graph
+        self.reserve = reserve_bytes
+        self.max_resident = max_resident
+        self.stream = torch.cuda.Stream()
+        self.log = log or (lambda *a: None)
+
+    def free_bytes(self):
+        import torch
+        free, total = torch.cuda.mem_get_info()
+        return free
+
+    def run(self, trace):
+        import torch
+        import paper_2110_05197_amd as M
+        waiting = sorted(trace, key=lambda r: r.arrival)
+        resident = []          # (req, sim, remaining)
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        done = []
+        with torch.cuda.stream(self.stream):
+            while waiting or resident:
+                # admit arrived requests while memory and slots allow
+                admitted_any = False
+                while waiting and waiting[0].arrival <= now() and len(resident) < self.max_resident:
+                    req = waiting[0]
+                    need = footprint(req) + 16 * (req.params["nx"] * req.params["ny"] * req.params["nz"])
+                    if self.free_bytes() - need < self.reserve and resident:
+                        break
+                    waiting.pop(0)
+                    sim = M.Sim(req.params, stream=self.stream)
+                    rR, rB = initial_fields(req)
+                    sim.init_equilibrium(rR, rB)
+                    req.admitted = now()
+                    resident.append([req, sim, req.steps])
+                    admitted_any = True
+                if not resident:
+                    # idle until the next arrival
+                    if waiting:
+                        time.sleep(max(0.0, min(0.01, waiting[0].arrival - now())))
+                    continue
+                batch = M.Batch([s for (_, s, _) in resident], [r for (_, _, r) in resident],
+                                stream=self.stream)
+                # replay K-step graphs until somebody finishes or new work arrives
+                while True:
+                    batch.step(self.k, use_graph=self.use_graph)
+                    st, steps = batch.status()
+                    finished = [i for i, s in enumerate(st) if s != M.RUNNING]
+                    arrived = bool(waiting) and waiting[0].arrival <= now()
+                    if finished or arrived:
+                        break
+                batch.close()
+                keep = []
+                for i, (req, sim, rem) in enumerate(resident):
+                    rem_now = rem - steps[i]
+                    req.steps_done += steps[i]
+                    if st[i] == M.RUNNING:
+                        keep.append([req, sim, rem_now])
+                        continue
+                    req.finished = now()
+                    req.outcome = "done" if st[i] == M.DONE else "diverged"
+                    if st[i] == M.DONE and sim.diverged():
+                        req.outcome = "diverged"
+                    done.append(req)
+                    sim.close()
+                    self.log(f"[serve] {req.rid} {req.outcome} after {req.steps_done} steps")
+                resident = keep
+        torch.cuda.synchronize()
+        return done, now()
+
+
+def serve_one_at_a_time(trace, check_every=1000, log=None):
+    """Reference: FIFO, one simulation at a time, FP64, two-pass kernels, no
+    graphs; a request cannot start before it arrives."""
+    import torch
+    import paper_2110_05197_amd as M
+    log = log or (lambda *a: None)
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    out = []
+    for req in sorted(trace, key=lambda r: r.arrival):
+        while now() < req.arrival:
+            time.sleep(min(0.01, req.arrival - now()))
+        p = dict(req.params, precision=M.FP64, kernel=M.KERNEL_TWO_PASS)
+        sim = M.Sim(p)
+        rR, rB = initial_fields(req)
+        sim.init_equilibrium(rR, rB)
+        req.admitted = now()
+        st, done = sim.step(req.steps, check_every=check_every)
+        torch.cuda.synchronize()
+        req.steps_done = done
+        req.finished = now()
+        req.outcome = "diverged" if st == M.DIVERGED else "done"
+        sim.close()
+        out.append(req)
+        log(f"[fifo] {req.rid} {req.outcome}")
+    return out, now()
+
+
+def summarize(reqs, wall):
+    lat = np.array([r.finished - r.arrival for r in reqs])
+    lups = sum(r.steps_done * r.params["nx"] * r.params["ny"] * r.params["nz"] for r in reqs)
+    outcomes = {}
+    for r in reqs:
+        key = f"{'CG' if r.params['model'] == 0 else 'SC'}:{r.outcome}"
+        outcomes[key] = outcomes.get(key, 0) + 1
+    div = [r for r in reqs if r.outcome == "diverged"]
+    outcomes["diverged_gamma_min"] = round(min((r.gamma for r in div), default=float("nan")), 2)
+    return dict(requests=len(reqs), wall_s=round(wall, 3),
+                throughput_req_s=round(len(reqs) / wall, 4),
+                glups=round(lups / wall / 1e9, 3),
+                p50_latency_s=round(float(np.percentile(lat, 50)), 4),
+                p99_latency_s=round(float(np.percentile(lat, 99)), 4),
+                outcomes=outcomes)

@@ -1,0 +1,68 @@
+"""Sweep serving on the GPU: continuous batching completes a small seeded
+trace, classifies diverging requests, and gives each request the same
+bits it gets when stepped alone."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_05197_amd as M
+    M.lib()
+    return M
+
+
+def test_small_trace_served_and_classified(M):
+    from paper_2110_05197_amd import serve
+    trace = serve.make_trace(n=12, rate=200.0, seed=3, d2_sizes=(32, 48), d3_sizes=(16, 24),
+                             steps_range=(100, 400))
+    # one request that must diverge: Shan-Chen far beyond its stable range
+    bad = trace[0]
+    bad.params = M.make_params(lattice=M.D3Q19, model=M.SC_MP, nx=16, ny=16, nz=16, G=-12.0,
+                               tau_R=0.52, rho0_R=2.0, rho0_B=0.2, precision=M.FP32)
+    bad.case = "droplet"
+    server = serve.Server(k_steps=25)
+    done, wall = server.run(trace)
+    assert len(done) == 12
+    by = {r.rid: r for r in done}
+    assert by[bad.rid].outcome == "diverged"
+    for r in done:
+        if r.outcome == "done":
+            assert r.steps_done == r.steps
+    s = serve.summarize(done, wall)
+    print(s, flush=True)
+    assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_served_result_equals_solo(M):
+    """A request's final populations are the same bits served in a mix as
+    stepped alone through the batch API."""
+    from paper_2110_05197_amd import serve
+    trace = serve.make_trace(n=5, rate=1000.0, seed=4, d2_sizes=(32,), d3_sizes=(16,),
+                             steps_range=(150, 250))
+    sims, results = [], []
+    for r in trace:
+        s = M.Sim(r.params)
+        s.init_equilibrium(*serve.initial_fields(r))
+        sims.append(s)
+    b = M.Batch(sims, [r.steps for r in trace])
+    for _ in range(30):
+        b.step(10)
+    st, steps = b.status()
+    b.close()
+    mixed = [s.export_f().cpu().numpy() for s in sims]
+    for r, fm, stt in zip(trace, mixed, st):
+        s = M.Sim(r.params)
+        s.init_equilibrium(*serve.initial_fields(r))
+        b1 = M.Batch([s], [r.steps])
+        for _ in range(30):
+            b1.step(10)
+        st1, _ = b1.status()
+        b1.close()
+        assert st1[0] == stt
+        assert np.array_equal(s.export_f().cpu().numpy(), fm)
