@@ -122,6 +122,18 @@ def serving_leg(full: bool):
                 outcome_agreement=f"{agree}/{len(done)}")
 
 
+def copy_probe(n: int):
+    """A plain copy of the bytes one FP32 step reads (and writes): 38 n^3 floats.
+    Counter readings of this kernel scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    a = torch.ones(38 * n ** 3, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,9 +147,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the sweep-serving leg")
     ap.add_argument("--serve-full", action="store_true",
                     help="serve the full 256-request trace (minutes) instead of the reduced one")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of one step's population bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.size)
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU slab decomposition is a design, not an implementation.", file=sys.stderr)
         sys.exit(2)
 

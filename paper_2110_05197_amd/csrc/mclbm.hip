@@ -206,16 +206,26 @@ const Ops *get_ops(int lattice, int precision, int model, bool rep)
 
 namespace mclbm {
 
-__global__ void k_obs_final(const double *__restrict__ partials, int nblocks, double *__restrict__ out)
+// Final reduction of the per-block partials: one block per accumulator,
+// each thread folds a fixed stride of partials, then a fixed LDS tree.
+__global__ __launch_bounds__(256) void k_obs_final(const double *__restrict__ partials, int nblocks,
+                                                   double *__restrict__ out)
 {
-    const int a = threadIdx.x;
-    if (a >= kNAcc) return;
-    double v = partials[a];
-    for (int b = 1; b < nblocks; ++b) {
+    __shared__ double s[256];
+    const int a = blockIdx.x;
+    const bool is_max = a == 6 || a == 8;
+    double v = is_max ? 0.0 : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
         const double w = partials[(long long)b * kNAcc + a];
-        v = (a == 6 || a == 8) ? fmax(v, w) : v + w;
+        v = is_max ? fmax(v, w) : v + w;
     }
-    out[a] = v;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] = is_max ? fmax(s[threadIdx.x], s[threadIdx.x + h]) : s[threadIdx.x] + s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[a] = s[0];
 }
 
 // Close one batch step: running simulations flip buffers and count the
@@ -509,7 +519,7 @@ mclbm_status mclbm_observables(mclbm_sim *sim, mclbm_obs *out)
     const int nb = (int)std::min<long long>(kRedBlocks, grid_of(sim->kp.N));
     sim->ops->density(sim->kp, sim->f[sim->cur], sim->field, sim->d_flag, sim->stream);
     sim->ops->obs(sim->kp, sim->f[sim->cur], sim->field, eps_table(), sim->d_partials, nb, sim->stream);
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, sim->stream, sim->d_partials, nb, sim->d_obs);
+    hipLaunchKernelGGL(k_obs_final, dim3(kNAcc), dim3(256), 0, sim->stream, sim->d_partials, nb, sim->d_obs);
     s = launched("observables");
     if (s) return s;
     MCLBM_HIP(hipMemcpyAsync(sim->h_obs, sim->d_obs, sizeof(double) * kNAcc, hipMemcpyDeviceToHost, sim->stream));
