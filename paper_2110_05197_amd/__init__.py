@@ -74,6 +74,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2110_05197_amd._build` (no CPU fallback exists)")
+        # The library must share the HIP runtime that owns the caller's device
+        # memory and streams.  Loading torch first puts its libamdhip64 in the
+        # process, and the library's dependency then resolves to that copy;
+        # loaded the other way round, two runtimes coexist and the second one
+        # sees no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         st = ctypes.c_int32
         sigs = {

@@ -5,6 +5,7 @@ import ctypes
 import math
 import os
 import re
+import sys
 
 import pytest
 
@@ -114,3 +115,16 @@ def test_unsupported_combinations(M):
 def test_d2q9_rejects_z_boundaries(M):
     with pytest.raises(M.MclbmError):
         M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, bc=(0, 0, 1)))
+
+
+def test_single_hip_runtime_when_library_loads_first():
+    """Loading the library before anything else imports torch must not map a
+    second HIP runtime (a second runtime sees no device)."""
+    import subprocess
+    code = ("import paper_2110_05197_amd as M; M.lib(); "
+            "maps = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
