@@ -43,27 +43,58 @@ class Request:
     info: dict = field(default_factory=dict)
 
 
-def sc_coexistence_ratio(G: float) -> float:
-    """Liquid/gas density ratio of the Shan-Chen multiphase model (psi = 1 -
-    exp(-rho)) under Guo forcing, from p(l) = p(g) and the integral of
-    (p - p0) psi'/psi over [g, l] being zero; nan below the critical |G| = 4."""
-    if G >= -4.0:
-        return float("nan")
-    from scipy.integrate import quad
-    from scipy.optimize import fsolve
-    psi = lambda r: 1 - np.exp(-r)
-    dpsi = lambda r: np.exp(-r)
-    pr = lambda r: r / 3 + G * psi(r) ** 2 / 6
+def sc_coexistence(G: float):
+    """Liquid and gas densities (l, g) of the Shan-Chen multiphase model with
+    psi = 1 - exp(-rho) under Guo forcing: p(l) = p(g) = p0 and the integral of
+    (p0 - p) psi'/psi over [g, l] vanishes, with p = rho/3 + G psi^2 / 6.
+    (nan, nan) at or above the critical coupling G = -4.
 
-    def eqs(v):
-        l, g = np.exp(v)
-        return [pr(l) - pr(g), quad(lambda r: (pr(r) - pr(l)) * dpsi(r) / psi(r), g, l, limit=200)[0]]
-    import warnings
-    with warnings.catch_warnings():
-        warnings.simplefilter("ignore")
-        sol = fsolve(eqs, [np.log(2.0), np.log(0.1)], full_output=True)
-    l, g = np.exp(sol[0])
-    return float(l / g) if sol[2] == 1 else float("nan")
+    The equation of state falls between its two spinodals, where dp/drho = 0,
+    i.e. 1 + G x (1 - x) = 0 with x = exp(-rho).  For a pressure p0 between
+    the local minimum and maximum, the gas root lies below the first spinodal
+    and the liquid root above the second; the equal-area integral changes sign
+    across that pressure range and is solved by bracketed root finding."""
+    if not G < -4.0:
+        return float("nan"), float("nan")
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+
+    def psi(r):
+        return -np.expm1(-r)
+
+    def pr(r):
+        return r / 3.0 + G * psi(r) ** 2 / 6.0
+
+    disc = math.sqrt(1.0 + 4.0 / G)
+    r_a = -math.log((1.0 + disc) / 2.0)     # local maximum of p
+    r_b = -math.log((1.0 - disc) / 2.0)     # local minimum of p
+    p_hi, p_lo = pr(r_a), max(pr(r_b), 0.0)
+
+    def roots(p0):
+        g = brentq(lambda r: pr(r) - p0, 0.0, r_a)
+        hi = r_b + 1.0
+        while pr(hi) < p0:
+            hi *= 2.0
+        l = brentq(lambda r: pr(r) - p0, r_b, hi)
+        return l, g
+
+    def area(p0):
+        l, g = roots(p0)
+        return quad(lambda r: (p0 - pr(r)) * math.exp(-r) / psi(r), g, l, limit=200)[0]
+
+    span = p_hi - p_lo
+    a, b = p_lo + 1e-12 * span, p_hi - 1e-12 * span
+    if area(a) * area(b) > 0:
+        return float("nan"), float("nan")
+    p0 = brentq(area, a, b, xtol=1e-14 * max(1.0, abs(p_hi)))
+    return roots(p0)
+
+
+def sc_coexistence_ratio(G: float) -> float:
+    """Liquid/gas density ratio of the Shan-Chen multiphase coexistence at G
+    (nan at or above the critical coupling)."""
+    l, g = sc_coexistence(G)
+    return float(l / g)
 
 
 _SC_TABLE = None
@@ -71,18 +102,30 @@ _SC_TABLE = None
 
 def sc_coupling_for_ratio(gamma: float) -> float:
     """G whose Shan-Chen coexistence has liquid/gas ratio gamma, interpolated
-    in log(ratio) on a table of the closed form over G in [-4.1, -8];
+    in log(ratio) on a table of the coexistence solution over G in [-4.02, -6.5];
     ratios beyond the table clamp to its strongest coupling."""
     global _SC_TABLE
     if _SC_TABLE is None:
-        Gs = np.linspace(-4.1, -8.0, 24)
+        Gs = np.linspace(-4.02, -6.5, 64)
         rs = np.array([sc_coexistence_ratio(g) for g in Gs])
         ok = np.isfinite(rs) & (rs > 1)
         Gs, rs = Gs[ok], rs[ok]
         order = np.argsort(rs)
         _SC_TABLE = (np.log(rs[order]), Gs[order])
     lr, Gs = _SC_TABLE
-    return float(np.interp(np.log(gamma), lr, Gs))
+    target = math.log(gamma)
+    G = float(np.interp(target, lr, Gs))
+    if not lr[0] < target < lr[-1]:
+        return G
+    # two secant steps on log(ratio) from the table's bracketing entries
+    k = int(np.searchsorted(lr, target))
+    G0, f0 = float(Gs[k - 1]), float(lr[k - 1]) - target
+    for _ in range(2):
+        f1 = math.log(sc_coexistence_ratio(G)) - target
+        if f1 == f0 or not math.isfinite(f1):
+            break
+        G, G0, f0 = G - f1 * (G - G0) / (f1 - f0), G, f1
+    return G
 
 
 def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 512),
@@ -131,8 +174,8 @@ def initial_fields(req: Request):
     shape = (p["nz"], p["ny"], p["nx"])
     L = p["nx"]
     if p["model"] == 1:
-        # SC multiphase: liquid droplet at ~2 in vapour ~0.2 (it relaxes to its coexistence)
-        rhoL, rhoG = 2.0, 0.2
+        # SC multiphase: liquid droplet in vapour at the coexistence densities of G
+        rhoL, rhoG = sc_coexistence(p["G"])
     else:
         rhoL, rhoG = p["rho0_R"], p["rho0_B"]
     if req.case == "droplet":
