@@ -207,8 +207,12 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
                 sc_collide_component<L, C, M>(c[K - 1], H.om[1], drc[1], rB, u, FB, H.rho0[1], H.corrM[1], H.shiftM[1]);
             }
             const long long n = n_xy + sxy * z;
-            if constexpr (PERIODIC) push_store_periodic<L, K>(P, dst, x, y, z, n, c);
-            else push_store_general<L, K>(P, dst, x, y, z, n, c);
+            // populations that stay on their x (cx = 0) land on whole cache
+            // lines and are never read again in this step: stream them past
+            // the cache; the x-shifted ones share lines with the neighbouring
+            // tile's stores and go through L2
+            if constexpr (PERIODIC) push_store_periodic<L, K, typename Prec<PR>::S, C, true>(P, dst, x, y, z, n, c);
+            else push_store_general<L, K, typename Prec<PR>::S, C, true>(P, dst, x, y, z, n, c);
         }
 
         // 3. stencil values of plane z+2

@@ -54,7 +54,9 @@ __device__ __forceinline__ void load_node(const S *__restrict__ f, long long N, 
 // (periodic wrap), bounces back into the opposite direction at the same node
 // when x + c_i is behind a wall, and leaves when it is behind an outflow face
 // only (the outflow completion supplies the entering populations afterwards).
-template <class L, int K, class S, class C, bool NT = false>
+// NTA: store the populations with c_x = 0 (whose targets keep the row's cache
+// line alignment) with the non-temporal hint.
+template <class L, int K, class S, class C, bool NTA = false>
 __device__ __forceinline__ void push_store_general(const KParams &P, S *__restrict__ dst, int x, int y, int z,
                                                    long long n, const C (&g)[K][L::Q])
 {
@@ -68,18 +70,21 @@ __device__ __forceinline__ void push_store_general(const KParams &P, S *__restri
         const int o = i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
         if (kind & 1) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) st<NT>(&(dst + (size_t)(k * L::Q + o) * N)[(unsigned)n], (S)g[k][i]);
+            for (int k = 0; k < K; ++k) st<false>(&(dst + (size_t)(k * L::Q + o) * N)[(unsigned)n], (S)g[k][i]);
         } else if (kind == 0) {
             const unsigned t = (unsigned)tx + (unsigned)P.nx * ((unsigned)ty + (unsigned)P.ny * (unsigned)tz);
 #pragma unroll
-            for (int k = 0; k < K; ++k) st<NT>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
+            for (int k = 0; k < K; ++k) {
+                if (NTA && L::cx[i] == 0) st<true>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
+                else st<false>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
+            }
         }
     }
 }
 
 // All-periodic push: the target of direction i is n + c_i . (1, nx, nx ny)
 // with a wrap correction on the faces, selected at compile time per i.
-template <class L, int K, class S, class C, bool NT = false>
+template <class L, int K, class S, class C, bool NTA = false>
 __device__ __forceinline__ void push_store_periodic(const KParams &P, S *__restrict__ dst, int x, int y, int z,
                                                     long long n, const C (&g)[K][L::Q])
 {
@@ -96,7 +101,10 @@ __device__ __forceinline__ void push_store_periodic(const KParams &P, S *__restr
         if (L::cz[i]) d += L::cz[i] > 0 ? dzp : dzm;
         const unsigned t = (unsigned)((int)n + d);
 #pragma unroll
-        for (int k = 0; k < K; ++k) st<NT>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
+        for (int k = 0; k < K; ++k) {
+            if (NTA && L::cx[i] == 0) st<true>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
+            else st<false>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
+        }
     }
 }
 
