@@ -58,18 +58,64 @@ def measured_traffic(kernel_name: str, per_launch_units: int):
         return None
 
 
-def workload_fields(n: int, seed: int = 0):
+MODELS = {"CG": 0, "SC_MP": 1, "SC_MC": 2}
+SC_MP_G, SC_MC_GRB = -5.0, 1.2
+
+
+def shape_of(n: int, lattice: str):
+    """D3Q19: n^3.  D2Q9: a square of the same node count (16 n x 16 n at n = 256)."""
+    if lattice == "D2Q9":
+        L = int(round(n ** 1.5))
+        return (1, L, L)
+    return (n, n, n)
+
+
+def workload_fields(n: int, seed: int = 0, model: str = "CG", lattice: str = "D3Q19"):
     from paper_2110_05197_amd import inputs
-    rR, rB, placed = inputs.random_droplets((n, n, n), 32 if n >= 128 else 4,
-                                            10.0 * n / 256, 24.0 * n / 256, seed)
+    shape = shape_of(n, lattice)
+    L = shape[2]
+    count = 32 if n >= 128 else 4
+    rmin, rmax = 10.0 * n / 256, 24.0 * n / 256
+    if lattice == "D2Q9":
+        count, rmin, rmax = 32, L / 40.0, L / 16.0
+    if model == "SC_MP":
+        from paper_2110_05197_amd import serve
+        liq, gas = serve.sc_coexistence(SC_MP_G)
+        rR, rB, _ = inputs.random_droplets(shape, count, rmin, rmax, seed, liq, gas)
+        return rR + rB, None
+    rR, rB, _ = inputs.random_droplets(shape, count, rmin, rmax, seed)
+    if model == "SC_MC":
+        return rR + 0.03, rB + 0.03
     return rR, rB
 
 
-def params(n: int, precision: int = 1, kernel: int = 0):
+def params(n: int, precision: int = 1, kernel: int = 0, model: str = "CG", lattice: str = "D3Q19"):
     import paper_2110_05197_amd as M
-    return M.make_params(lattice=M.D3Q19, model=M.CG, precision=precision, nx=n, ny=n, nz=n,
-                         rho0_R=1.0, rho0_B=1.0, tau_R=1.0, tau_B=1.0, A=0.005, beta=0.7,
-                         kernel=kernel)
+    nz, ny, nx = shape_of(n, lattice)
+    base = dict(lattice=M.D2Q9 if lattice == "D2Q9" else M.D3Q19, precision=precision, nx=nx, ny=ny,
+                nz=nz, kernel=kernel)
+    if model == "SC_MP":
+        return M.make_params(model=M.SC_MP, G=SC_MP_G, tau_R=1.0, rho0_R=2.0, rho0_B=0.15, **base)
+    if model == "SC_MC":
+        return M.make_params(model=M.SC_MC, G_RB=SC_MC_GRB, tau_R=1.0, tau_B=1.0, rho0_R=1.0,
+                             rho0_B=1.0, **base)
+    return M.make_params(model=M.CG, rho0_R=1.0, rho0_B=1.0, tau_R=1.0, tau_B=1.0, A=0.005,
+                         beta=0.7, **base)
+
+
+def stream_probe(n: int):
+    """Ceilings of the step's memory pattern: the committed stream probe (built
+    next to the library) moving one FP32 D3Q19 step's bytes in each pattern."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2110_05197_amd", "stream_probe")
+    if not os.path.exists(exe):
+        print("bench.py: stream_probe is not built (run __graft_entry__.build())", file=sys.stderr)
+        sys.exit(1)
+    r = subprocess.run([exe, str(n)], capture_output=True, text=True, timeout=600)
+    sys.stdout.write(r.stdout)
+    if r.returncode:
+        sys.stderr.write(r.stderr)
+        sys.exit(r.returncode)
 
 
 def cpu_baseline(rR, rB, n: int, steps: int):
@@ -149,9 +195,16 @@ def main():
                     help="serve the full 256-request trace (minutes) instead of the reduced one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one step's population bytes (counter calibration)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only time the step's memory patterns without stencil or collision (ceilings)")
+    ap.add_argument("--model", default="CG", choices=sorted(MODELS))
+    ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.size)
+        return
+    if args.stream_probe:
+        stream_probe(args.size)
         return
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -164,9 +217,10 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     n = args.size
-    print(f"[bench] generating {n}^3 fields", file=sys.stderr, flush=True)
-    rR, rB = workload_fields(n)
-    p = params(n, args.precision, args.kernel)
+    headline = args.model == "CG" and args.lattice == "D3Q19"
+    print(f"[bench] generating {args.lattice} {args.model} fields ({n}^3 nodes)", file=sys.stderr, flush=True)
+    rR, rB = workload_fields(n, 0, args.model, args.lattice)
+    p = params(n, args.precision, args.kernel, args.model, args.lattice)
     sim = M.Sim(p)
     sim.init_equilibrium(rR, rB)
     stream = torch.cuda.current_stream()
@@ -183,20 +237,20 @@ def main():
     ms_total = ev0.elapsed_time(ev1)
     ms = ms_total / args.steps
     o1 = sim.observables()
-    N = n ** 3
+    N = p["nx"] * p["ny"] * p["nz"]
     mlups = N / (ms * 1e-3) / 1e6
     bpu = M.bytes_per_update(p)
     achieved = bpu * N / (ms * 1e-3) / 1e9
-    fused = sim.params.get("kernel", 0) != 1
-    drift = abs(o1["mass_R"] - o0["mass_R"]) / o0["mass_R"]
+    fused = sim.kernel_used() == M.KERNEL_FUSED
+    drift = abs(o1["mass_R"] - o0["mass_R"]) / o0["mass_R"] if o0["mass_R"] else 0.0
     print(f"[bench] {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, "
           f"mass drift {drift:.2e}, diverged={o1['diverged']}", file=sys.stderr, flush=True)
-    traffic = measured_traffic("k_fused", N) if (fused and args.precision == 1 and n == 256) else None
+    traffic = measured_traffic("k_fused", N) if (fused and headline and args.precision == 1 and n == 256) else None
     del sim
     torch.cuda.empty_cache()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and headline:
         print(f"[bench] cpu baseline ({args.cpu_steps} oracle steps)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(rR, rB, n, args.cpu_steps)
 
@@ -206,7 +260,7 @@ def main():
 
     dtype = {0: "f64", 1: "f32", 2: "f32+f64", 3: "f16-storage/f32"}[args.precision]
     out = {
-        "metric": METRIC,
+        "metric": METRIC if headline else f"{args.lattice} {args.model} MLUPS + % HBM roofline",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -219,9 +273,12 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {
-            "workload": f"D3Q19 colour-gradient step, {n}^3 periodic, 32 seeded droplets r~U[10,24], "
-                        "gamma=1, tau=1, A=0.005, beta=0.7",
-            "lattice": "D3Q19", "model": "CG", "nx": n, "ny": n, "nz": n,
+            "workload": (f"D3Q19 colour-gradient step, {n}^3 periodic, 32 seeded droplets r~U[10,24], "
+                         "gamma=1, tau=1, A=0.005, beta=0.7") if headline else
+                        (f"{args.lattice} {args.model} step, {p['nx']}x{p['ny']}x{p['nz']} periodic, 32 seeded "
+                         "droplets" + (f", G={SC_MP_G} at coexistence" if args.model == "SC_MP" else "")
+                         + (f", G_RB={SC_MC_GRB}" if args.model == "SC_MC" else "")),
+            "lattice": args.lattice, "model": args.model, "nx": p["nx"], "ny": p["ny"], "nz": p["nz"],
             "precision": dtype, "kernel": "fused one-pass" if fused else "two-pass",
             "parallelism": "single GPU",
         },

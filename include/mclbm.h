@@ -54,7 +54,7 @@ extern "C" {
 #endif
 
 #define MCLBM_VERSION_MAJOR 1
-#define MCLBM_VERSION_MINOR 0
+#define MCLBM_VERSION_MINOR 1
 #define MCLBM_ABI_VERSION 1
 
 typedef int32_t mclbm_status;
@@ -222,6 +222,11 @@ mclbm_status mclbm_restore(mclbm_sim *sim, const void *d_src, int64_t step);
 
 /* Read the device divergence flag (synchronises): 1 if set. */
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged);
+
+/* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass,
+ * D3Q19 float paths without the repulsion force, nx % 32 == 0 and
+ * ny % 4 == 0) or MCLBM_KERNEL_TWO_PASS.  Host only; EINVAL on NULL. */
+mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
 
 /* ------------------------------------------------------------------------ */
 /* Batched stepping of many independent simulations (sweep serving).         */

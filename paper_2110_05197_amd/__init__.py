@@ -101,6 +101,7 @@ def lib():
             "mclbm_checkpoint": [_vp, _vp, ctypes.POINTER(ctypes.c_int64)],
             "mclbm_restore": [_vp, _vp, ctypes.c_int64],
             "mclbm_diverged": [_vp, ctypes.POINTER(ctypes.c_int32)],
+            "mclbm_kernel_used": [_vp, ctypes.POINTER(ctypes.c_int32)],
             "mclbm_batch_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                    _vp, ctypes.POINTER(_vp)],
             "mclbm_batch_step": [_vp, ctypes.c_int32, ctypes.c_int32],
@@ -307,6 +308,12 @@ class Sim:
         d = ctypes.c_int32()
         _check(lib().mclbm_diverged(self._h, ctypes.byref(d)), "mclbm_diverged")
         return bool(d.value)
+
+    def kernel_used(self) -> int:
+        """KERNEL_FUSED or KERNEL_TWO_PASS: the step kernel this simulation runs."""
+        k = ctypes.c_int32()
+        _check(lib().mclbm_kernel_used(self._h, ctypes.byref(k)), "mclbm_kernel_used")
+        return k.value
 
 
 class Batch:

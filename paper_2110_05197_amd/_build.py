@@ -16,6 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmclbm.so")
+PROBE = os.path.join(PKG, "stream_probe")
 SOURCES = ["mclbm.hip", "inst_p0.hip", "inst_p1.hip", "inst_p2.hip", "inst_p3.hip"]
 ARCH = os.environ.get("MCLBM_OFFLOAD_ARCH", "gfx950")
 
@@ -41,16 +42,29 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _build_probe() -> str:
+    """The stream-pattern bandwidth probe (measurement only, not the library)."""
+    cmd = ["hipcc", *[f for f in FLAGS if f != "-fPIC"], "-o", PROBE + ".tmp",
+           os.path.join(CSRC, "stream_probe.hip")]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for stream_probe.hip:\n{r.stdout}")
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    jobs = min(len(SOURCES) + 1, max(1, (os.cpu_count() or 2)))
     with ThreadPoolExecutor(jobs) as ex:
+        probe = ex.submit(_build_probe)
         objs = list(ex.map(_compile, SOURCES))
+        probe.result()
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PROBE)
     return LIB
 
 

@@ -465,6 +465,13 @@ mclbm_status mclbm_init_equilibrium(mclbm_sim *sim, const double *d_rhoR, const 
     return launched("init");
 }
 
+mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel)
+{
+    if (!sim || !kernel) return fail(MCLBM_EINVAL, "null argument");
+    *kernel = sim->fused ? MCLBM_KERNEL_FUSED : MCLBM_KERNEL_TWO_PASS;
+    return MCLBM_OK;
+}
+
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged)
 {
     if (!sim || !diverged) return fail(MCLBM_EINVAL, "NULL argument");

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_function(M):
 
 
 def test_version_and_status_strings(M):
-    assert M.version() == (1, 0)
+    assert M.version() == (1, 1)
     L = M.lib()
     for s in (0, 1, -1, -2, -3, -4):
         assert L.mclbm_status_str(s)

@@ -384,3 +384,21 @@ def test_batch_stops_diverged_member(M):
     st, steps = b.status()
     assert st == [M.DONE, M.STOPPED_DIVERGED]
     assert steps[0] == 30 and steps[1] == 1
+
+
+def test_kernel_used_reports_the_dispatch(M):
+    """mclbm_kernel_used: fused for D3Q19 float paths on 32/4-divisible
+    boxes, two-pass otherwise (FP64, D2Q9, ragged x, forced two-pass)."""
+    def used(**kw):
+        s = M.Sim(M.make_params(**kw))
+        k = s.kernel_used()
+        s.close()
+        return k
+    d3 = dict(lattice=M.D3Q19, nx=64, ny=16, nz=8)
+    assert used(precision=M.FP32, **d3) == M.KERNEL_FUSED
+    assert used(precision=M.MIXED, **d3) == M.KERNEL_FUSED
+    assert used(precision=M.FP16, **d3) == M.KERNEL_FUSED
+    assert used(precision=M.FP64, **d3) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP32, kernel=M.KERNEL_TWO_PASS, **d3) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP32, lattice=M.D3Q19, nx=40, ny=16, nz=8) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP32, lattice=M.D2Q9, nx=64, ny=64, nz=1) == M.KERNEL_TWO_PASS
