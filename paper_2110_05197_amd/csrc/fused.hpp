@@ -149,10 +149,10 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
     for (int z = z0; z < z1; ++z) {
         // 1. issue the loads of plane z+2 (consumed after the collision)
         const bool ahead = z + 2 <= z1;
-        C d[K][Q], hh[K][Q];
+        RawNode<L, K, typename Prec<PR>::S, C> dr_, hr_;
         if (ahead) {
-            load_node<L, K>(src, N, n_xy + zoff(z + 2), d);
-            if (has_h) load_node<L, K>(src, N, h_xy + zoff(z + 2), hh);
+            dr_.load(src, N, n_xy + zoff(z + 2));
+            if (has_h) hr_.load(src, N, h_xy + zoff(z + 2));
         }
 
         // 2. collide plane z with the stencil values of planes z-1, z, z+1
@@ -217,9 +217,13 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
 
         // 3. stencil values of plane z+2
         M drd[2], jd[3];
+        C d[K][Q];
+        dr_.get(d);
         if (ahead) {
             put(z + 2, my_slot, d, drd, jd, true);
             if (has_h) {
+                C hh[K][Q];
+                hr_.get(hh);
                 M dh[2], jh[3];
                 put(z + 2, h_slot, hh, dh, jh, false);
             }

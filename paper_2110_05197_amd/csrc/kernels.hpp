@@ -5,6 +5,8 @@
 // kernels and the batched kernels run the very same arithmetic.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "node.hpp"
@@ -39,15 +41,90 @@ template <bool NT, class T> __device__ __forceinline__ void st(T *p, T v)
     else *p = v;
 }
 
+// Storage order.  Two-colour FP16 storage keeps both colours of a population
+// in one 32-bit word, [i][n][k], so that a node moves 19 dwords each way as in
+// FP32 (2-byte accesses would halve the payload of every memory instruction);
+// every other storage is [k][i][n].
+using Half2 = _Float16 __attribute__((ext_vector_type(2)));
+template <int K, class S> constexpr bool kPairs = K == 2 && std::is_same<S, _Float16>::value;
+
+template <class L, int K, class S>
+__device__ __forceinline__ size_t sidx(int k, int i, size_t N, size_t n)
+{
+    if constexpr (kPairs<K, S>) return 2 * ((size_t)i * N + n) + (size_t)k;
+    else return (size_t)(k * L::Q + i) * N + n;
+}
+
 template <class L, int K, class S, class C, bool NT = false>
 __device__ __forceinline__ void load_node(const S *__restrict__ f, long long N, long long n,
                                           C (&g)[K][L::Q])
 {
     const unsigned o = (unsigned)n;   // N < 2^31: per-lane 32-bit offset, uniform base
+    if constexpr (kPairs<K, S>) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int i = 0; i < L::Q; ++i) {
+            const Half2 v = ld<NT>(&(reinterpret_cast<const Half2 *>(f) + (size_t)i * (size_t)N)[o]);
+            g[0][i] = (C)v.x;
+            g[1][i] = (C)v.y;
+        }
+    } else {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) g[k][i] = (C)ld<NT>(&(f + (size_t)(k * L::Q + i) * (size_t)N)[o]);
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) g[k][i] = (C)ld<NT>(&(f + (size_t)(k * L::Q + i) * (size_t)N)[o]);
+    }
+}
+
+// A node's populations held as loaded, for software prefetching: the load is
+// issued early and the conversion to the arithmetic type waits until the
+// values are used (converting on arrival would wait for the load at once).
+template <class L, int K, class S, class C, bool PAIRS = kPairs<K, S>>
+struct RawNode {
+    C v[K][L::Q];
+    __device__ __forceinline__ void load(const S *__restrict__ f, long long N, long long n)
+    {
+        load_node<L, K>(f, N, n, v);
+    }
+    __device__ __forceinline__ void get(C (&g)[K][L::Q]) const
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) g[k][i] = v[k][i];
+    }
+};
+template <class L, int K, class S, class C>
+struct RawNode<L, K, S, C, true> {
+    Half2 v[L::Q];
+    __device__ __forceinline__ void load(const S *__restrict__ f, long long N, long long n)
+    {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) v[i] = (reinterpret_cast<const Half2 *>(f) + (size_t)i * (size_t)N)[(unsigned)n];
+    }
+    __device__ __forceinline__ void get(C (&g)[K][L::Q]) const
+    {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            g[0][i] = (C)v[i].x;
+            g[1][i] = (C)v[i].y;
+        }
+    }
+};
+
+// Population i of every colour of g stored into slot j of node t.
+template <class L, int K, class S, class C, bool NT>
+__device__ __forceinline__ void store_pop(S *__restrict__ dst, size_t N, unsigned t, int j, int i,
+                                          const C (&g)[K][L::Q])
+{
+    if constexpr (kPairs<K, S>) {
+        Half2 v;
+        v.x = (S)g[0][i];
+        v.y = (S)g[1][i];
+        st<NT>(&(reinterpret_cast<Half2 *>(dst) + (size_t)j * N)[t], v);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) st<NT>(&(dst + (size_t)(k * L::Q + j) * N)[t], (S)g[k][i]);
+    }
 }
 
 // Streaming as a push from node (x, y, z): population i goes to x + c_i
@@ -69,15 +146,11 @@ __device__ __forceinline__ void push_store_general(const KParams &P, S *__restri
         const int tz = push_coord(z + L::cz[i], P.nz, P.bc[2], kind);
         const int o = i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
         if (kind & 1) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) st<false>(&(dst + (size_t)(k * L::Q + o) * N)[(unsigned)n], (S)g[k][i]);
+            store_pop<L, K, S, C, false>(dst, N, (unsigned)n, o, i, g);
         } else if (kind == 0) {
             const unsigned t = (unsigned)tx + (unsigned)P.nx * ((unsigned)ty + (unsigned)P.ny * (unsigned)tz);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (NTA && L::cx[i] == 0) st<true>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
-                else st<false>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
-            }
+            if (NTA && L::cx[i] == 0) store_pop<L, K, S, C, true>(dst, N, t, i, i, g);
+            else store_pop<L, K, S, C, false>(dst, N, t, i, i, g);
         }
     }
 }
@@ -100,11 +173,8 @@ __device__ __forceinline__ void push_store_periodic(const KParams &P, S *__restr
         if (L::cy[i]) d += L::cy[i] > 0 ? dyp : dym;
         if (L::cz[i]) d += L::cz[i] > 0 ? dzp : dzm;
         const unsigned t = (unsigned)((int)n + d);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (NTA && L::cx[i] == 0) st<true>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
-            else st<false>(&(dst + (size_t)(k * L::Q + i) * N)[t], (S)g[k][i]);
-        }
+        if (NTA && L::cx[i] == 0) store_pop<L, K, S, C, true>(dst, N, t, i, i, g);
+        else store_pop<L, K, S, C, false>(dst, N, t, i, i, g);
     }
 }
 
@@ -304,7 +374,7 @@ __device__ __forceinline__ void outflow_body(const KParams &P, S *__restrict__ d
         if (P.bc[2] == 2 && (z - L::cz[i] < 0 || z - L::cz[i] >= P.nz)) iz += z == 0 ? 1 : -1;
         const long long m = (long long)ix + (long long)P.nx * ((long long)iy + (long long)P.ny * iz);
 #pragma unroll
-        for (int k = 0; k < K; ++k) dst[(long long)(k * L::Q + i) * N + n] = dst[(long long)(k * L::Q + i) * N + m];
+        for (int k = 0; k < K; ++k) dst[sidx<L, K, S>(k, i, N, n)] = dst[sidx<L, K, S>(k, i, N, m)];
     }
 }
 
@@ -369,15 +439,15 @@ __device__ __forceinline__ void init_body(const KParams &P, const double *__rest
         const double rR = rhoR[n], rB = rhoB[n], r = rR + rB;
         const double nub = 1.0 / ((rR / r) * P.inv_nu[0] + (rB / r) * P.inv_nu[1]);
         for (int i = 0; i < L::Q; ++i) {
-            f[(long long)i * N + n] = (S)cg_eq_dev<L>(P, 0, i, rR, u, gR, nub);
-            f[(long long)(L::Q + i) * N + n] = (S)cg_eq_dev<L>(P, 1, i, rB, u, gB, nub);
+            f[sidx<L, 2, S>(0, i, N, n)] = (S)cg_eq_dev<L>(P, 0, i, rR, u, gR, nub);
+            f[sidx<L, 2, S>(1, i, N, n)] = (S)cg_eq_dev<L>(P, 1, i, rB, u, gB, nub);
         }
     } else if constexpr (MODEL == SC_MP) {
-        for (int i = 0; i < L::Q; ++i) f[(long long)i * N + n] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
+        for (int i = 0; i < L::Q; ++i) f[sidx<L, 1, S>(0, i, N, n)] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
     } else {
         for (int i = 0; i < L::Q; ++i) {
-            f[(long long)i * N + n] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
-            f[(long long)(L::Q + i) * N + n] = (S)sc_eq_dev<L>(P, 1, i, rhoB[n], u);
+            f[sidx<L, 2, S>(0, i, N, n)] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
+            f[sidx<L, 2, S>(1, i, N, n)] = (S)sc_eq_dev<L>(P, 1, i, rhoB[n], u);
         }
     }
 }

@@ -69,10 +69,11 @@ __global__ __launch_bounds__(kBlock) void k_export(KParams P, const typename Pre
 {
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= P.N) return;
-    for (int k = 0; k < NComp<MODEL>::n; ++k)
+    constexpr int K = NComp<MODEL>::n;
+    for (int k = 0; k < K; ++k)
         for (int i = 0; i < L::Q; ++i) {
             const long long a = (long long)(k * L::Q + i) * P.N + n;
-            out[a] = (double)f[a] + P.shift[k][L::grp[i]];
+            out[a] = (double)f[sidx<L, K, typename Prec<PR>::S>(k, i, P.N, n)] + P.shift[k][L::grp[i]];
         }
 }
 
@@ -82,10 +83,11 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams P, const double *__re
 {
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= P.N) return;
-    for (int k = 0; k < NComp<MODEL>::n; ++k)
+    constexpr int K = NComp<MODEL>::n;
+    for (int k = 0; k < K; ++k)
         for (int i = 0; i < L::Q; ++i) {
             const long long a = (long long)(k * L::Q + i) * P.N + n;
-            f[a] = (typename Prec<PR>::S)(in[a] - P.shift[k][L::grp[i]]);
+            f[sidx<L, K, typename Prec<PR>::S>(k, i, P.N, n)] = (typename Prec<PR>::S)(in[a] - P.shift[k][L::grp[i]]);
         }
 }
 
