@@ -223,9 +223,9 @@ mclbm_status mclbm_restore(mclbm_sim *sim, const void *d_src, int64_t step);
 /* Read the device divergence flag (synchronises): 1 if set. */
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged);
 
-/* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass,
- * D3Q19 float paths without the repulsion force, nx % 32 == 0 and
- * ny % 4 == 0) or MCLBM_KERNEL_TWO_PASS.  Host only; EINVAL on NULL. */
+/* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass:
+ * D3Q19 without the repulsion force, nx % 32 == 0 and ny % 4 == 0) or
+ * MCLBM_KERNEL_TWO_PASS.  Host only; EINVAL on NULL. */
 mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
 
 /* ------------------------------------------------------------------------ */

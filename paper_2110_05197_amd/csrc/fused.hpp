@@ -251,9 +251,11 @@ struct FusedShape {
     int tx, ty, tz;
 };
 
-// Tile choice: TX = 64 when nx allows, else 32; TY the largest of 8, 4, 2, 1
-// dividing ny; TZ planes per block.
-inline bool fused_shape(const KParams &P, FusedShape &sh)
+// Tile choice: TX = 64 when nx allows, else 32; TY = 8 when ny allows, else
+// 4; TZ planes per block.  FP64 (wide) tiles are 4 rows: half the threads, so
+// that each wave may hold its double-precision planes in up to 512 registers
+// and the LDS slot of plane z+1 stays at the FP32 size.
+inline bool fused_shape(const KParams &P, FusedShape &sh, bool wide = false)
 {
     if (P.nx % 64 == 0) sh.tx = 64;
     else if (P.nx % 32 == 0) sh.tx = 32;
@@ -261,7 +263,10 @@ inline bool fused_shape(const KParams &P, FusedShape &sh)
     sh.ty = 0;
     const int cand[2] = {8, 4};
     for (int c : cand)
-        if (P.ny % c == 0 && (sh.tx + 2) * (c + 2) - sh.tx * c <= sh.tx * c) { sh.ty = c; break; }
+        if (!(wide && c == 8) && P.ny % c == 0 && (sh.tx + 2) * (c + 2) - sh.tx * c <= sh.tx * c) {
+            sh.ty = c;
+            break;
+        }
     if (!sh.ty) return false;
     // z-chunk: about one block per compute unit (256 on MI355X) -- more
     // resident blocks per XCD overflow its L2 and the halo re-reads miss
@@ -298,8 +303,11 @@ template <int PR, int MODEL>
 void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s)
 {
     FusedShape sh;
-    fused_shape(P, sh);  // checked at create time
-    if (sh.tx == 64) {
+    fused_shape(P, sh, PR == 0);  // checked at create time
+    if constexpr (PR == 0) {
+        if (sh.tx == 64) launch_fused_shape<PR, MODEL, 64, 4>(P, src, dst, flag, sh.tz, s);
+        else launch_fused_shape<PR, MODEL, 32, 4>(P, src, dst, flag, sh.tz, s);
+    } else if (sh.tx == 64) {
         if (sh.ty == 8) launch_fused_shape<PR, MODEL, 64, 8>(P, src, dst, flag, sh.tz, s);
         else launch_fused_shape<PR, MODEL, 64, 4>(P, src, dst, flag, sh.tz, s);
     } else {

@@ -69,7 +69,7 @@ KParams make_kparams(const mclbm_params &p);
 bool fused_ok(const mclbm_params &p, const Ops *ops)
 {
     FusedShape sh;
-    return ops && ops->has_fused() && fused_shape(make_kparams(p), sh);
+    return ops && ops->has_fused() && fused_shape(make_kparams(p), sh, p.precision == MCLBM_FP64);
 }
 
 mclbm_status validate(const mclbm_params *p)

@@ -43,7 +43,7 @@ inline long long outflow_count(const KParams &P)
 // Fused one-pass step (fused.hpp) for D3Q19 without the repulsion force.
 template <class L, int PR, int MODEL, bool REP> constexpr bool fused_available()
 {
-    return L::Q == 19 && !REP && PR != 0;
+    return L::Q == 19 && !REP;
 }
 template <int PR, int MODEL>
 void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);

@@ -264,19 +264,23 @@ def test_fp32_mass_conservation(M):
     assert abs(o1["mass_B"] - o0["mass_B"]) / o0["mass_B"] < 500 * 2e-7
 
 
-def test_fused_equals_two_pass_bitwise(M):
+@pytest.mark.parametrize("prec", [1, 0, 2, 3])
+def test_fused_equals_two_pass_bitwise(M, prec):
+    """The one-pass kernel and the two-pass kernels give bitwise identical
+    populations (same node arithmetic), for every precision path, periodic
+    and walls + outflow, all three models."""
     for bc in ((0, 0, 0), (1, 1, 2)):
         for model in (0, 1, 2):
             shape = (20, 16, 64)
             kw = dict(G=-5.0, rho0_R=1.9, rho0_B=0.12) if model == 1 else dict(G_RB=1.2, A=0.02)
-            p = M.make_params(lattice=M.D3Q19, model=model, precision=M.FP32, nx=64, ny=16, nz=20,
+            p = M.make_params(lattice=M.D3Q19, model=model, precision=prec, nx=64, ny=16, nz=20,
                               bc=bc, **kw)
             if model == 1:
                 a, b = inputs.droplet(shape, 5.0, 1.9, 0.12)
                 rR, rB = a + b, None
             else:
                 rR, rB, _ = cg_droplet_case(shape, 21)
-            say(f"[bitwise] fused vs two-pass bc={bc} model={model}")
+            say(f"[bitwise] fused vs two-pass prec={prec} bc={bc} model={model}")
             _, f1 = gpu_run(M, p, rR, rB, None, 37, kernel=1)
             _, f2 = gpu_run(M, p, rR, rB, None, 37, kernel=2)
             assert np.array_equal(f1, f2)
@@ -387,8 +391,8 @@ def test_batch_stops_diverged_member(M):
 
 
 def test_kernel_used_reports_the_dispatch(M):
-    """mclbm_kernel_used: fused for D3Q19 float paths on 32/4-divisible
-    boxes, two-pass otherwise (FP64, D2Q9, ragged x, forced two-pass)."""
+    """mclbm_kernel_used: fused for D3Q19 on 32/4-divisible boxes, two-pass
+    otherwise (D2Q9, ragged x or y, forced two-pass)."""
     def used(**kw):
         s = M.Sim(M.make_params(**kw))
         k = s.kernel_used()
@@ -398,7 +402,8 @@ def test_kernel_used_reports_the_dispatch(M):
     assert used(precision=M.FP32, **d3) == M.KERNEL_FUSED
     assert used(precision=M.MIXED, **d3) == M.KERNEL_FUSED
     assert used(precision=M.FP16, **d3) == M.KERNEL_FUSED
-    assert used(precision=M.FP64, **d3) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP64, **d3) == M.KERNEL_FUSED
+    assert used(precision=M.FP64, lattice=M.D3Q19, nx=64, ny=18, nz=8) == M.KERNEL_TWO_PASS
     assert used(precision=M.FP32, kernel=M.KERNEL_TWO_PASS, **d3) == M.KERNEL_TWO_PASS
     assert used(precision=M.FP32, lattice=M.D3Q19, nx=40, ny=16, nz=8) == M.KERNEL_TWO_PASS
     assert used(precision=M.FP32, lattice=M.D2Q9, nx=64, ny=64, nz=1) == M.KERNEL_TWO_PASS
