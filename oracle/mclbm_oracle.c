@@ -897,3 +897,139 @@ void orc_observables(const orc_params *p, const double *f, double *out)
     out[10] = vol; out[11] = nin; out[12] = nout; out[13] = diverged;
     free(rR); free(rB); free(j); free(psi);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Interface observables (the measurement procedures of the oscillation,     */
+/* ligament, coalescence and emulsion studies).                              */
+/*                                                                           */
+/* Phase indicator per node: phi = rho^N = (rho_R - rho_B)/rho for the two-  */
+/* component models, phi = rho - (rho0_R + rho0_B)/2 for SC multiphase (the  */
+/* interface definitions of the droplet-oscillation section); a node is      */
+/* inside the red (liquid) phase when phi > 0.                               */
+/* ------------------------------------------------------------------------ */
+void orc_phase_indicator(const orc_params *p, const double *f, double *phi)
+{
+    orc_lattice L;
+    get_lattice(p->lattice, &L);
+    const int64_t N = nnodes(p);
+    double *rR = calloc((size_t)N, sizeof(double));
+    double *rB = calloc((size_t)N, sizeof(double));
+    double *j = calloc((size_t)(3 * N), sizeof(double));
+    moments_pass(p, &L, f, rR, rB, j);
+    const double mid = 0.5 * (p->rho0_R + p->rho0_B);
+    for (int64_t n = 0; n < N; ++n) {
+        if (p->model == 1) phi[n] = rR[n] - mid;
+        else phi[n] = (rR[n] - rB[n]) / (rR[n] + rB[n]);
+    }
+    free(rR); free(rB); free(j);
+}
+
+/* Line along `axis` through the node whose other two coordinates are (c1,
+ * c2) in increasing axis order: the positions where the phase indicator
+ * changes side, each by linear interpolation between the two nodes of the
+ * crossing segment (the radius measurement of the droplet-oscillation
+ * section), in ascending order; on a periodic axis the segment from the last
+ * node to the first is included (position between n-1 and n).  Returns the
+ * number of crossings, of which the first `max` are written. */
+int orc_interface_crossings(const orc_params *p, const double *f, int axis, int c1, int c2,
+                            double *out, int max)
+{
+    const int64_t N = nnodes(p);
+    double *phi = calloc((size_t)N, sizeof(double));
+    orc_phase_indicator(p, f, phi);
+    const int len = axis == 0 ? p->nx : (axis == 1 ? p->ny : p->nz);
+    double *line = calloc((size_t)len, sizeof(double));
+    for (int s = 0; s < len; ++s) {
+        int x, y, z;
+        if (axis == 0) { x = s; y = c1; z = c2; }
+        else if (axis == 1) { x = c1; y = s; z = c2; }
+        else { x = c1; y = c2; z = s; }
+        line[s] = phi[idx(p, x, y, z)];
+    }
+    int count = 0;
+    const int segs = p->bc[axis] == 0 && len > 1 ? len : len - 1;
+    for (int s = 0; s < segs; ++s) {
+        const double a = line[s], b = line[(s + 1) % len];
+        if ((a > 0.0) != (b > 0.0)) {
+            if (count < max) out[count] = s + a / (a - b);
+            ++count;
+        }
+    }
+    free(line); free(phi);
+    return count;
+}
+
+/* Phase area of the lattice plane `pos` normal to `axis`: the sum of the red
+ * fraction (1 + rho^N)/2 over the plane for the two-component models, the
+ * count of nodes with rho >= (rho0_R + rho0_B)/2 for SC multiphase (the red
+ * volume of the observables, restricted to one plane; the bridge radius of
+ * the coalescence study is sqrt(area / pi)). */
+double orc_plane_area(const orc_params *p, const double *f, int axis, int pos)
+{
+    orc_lattice L;
+    get_lattice(p->lattice, &L);
+    const int64_t N = nnodes(p);
+    double *rR = calloc((size_t)N, sizeof(double));
+    double *rB = calloc((size_t)N, sizeof(double));
+    double *j = calloc((size_t)(3 * N), sizeof(double));
+    moments_pass(p, &L, f, rR, rB, j);
+    const double mid = 0.5 * (p->rho0_R + p->rho0_B);
+    double area = 0.0;
+    for (int64_t n = 0; n < N; ++n) {
+        int x, y, z;
+        coords(p, n, &x, &y, &z);
+        const int c = axis == 0 ? x : (axis == 1 ? y : z);
+        if (c != pos) continue;
+        const double r = rR[n] + rB[n];
+        if (p->model == 1) area += r >= mid ? 1.0 : 0.0;
+        else area += 0.5 * (1.0 + (rR[n] - rB[n]) / r);
+    }
+    free(rR); free(rB); free(j);
+    return area;
+}
+
+/* Connected components of the inside nodes (phi > 0) under face adjacency,
+ * wrapping across periodic faces (droplet counting of the emulsion study).
+ * labels[n] = smallest node index of n's component, -1 outside.  Breadth-
+ * first search started from the nodes in ascending index order.  Returns the
+ * number of components. */
+int64_t orc_label_components(const orc_params *p, const double *f, int64_t *labels)
+{
+    const int64_t N = nnodes(p);
+    double *phi = calloc((size_t)N, sizeof(double));
+    orc_phase_indicator(p, f, phi);
+    int64_t *queue = malloc((size_t)N * sizeof(int64_t));
+    for (int64_t n = 0; n < N; ++n) labels[n] = -1;
+    const int dims[3] = {p->nx, p->ny, p->nz};
+    int64_t count = 0;
+    for (int64_t s = 0; s < N; ++s) {
+        if (!(phi[s] > 0.0) || labels[s] >= 0) continue;
+        ++count;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        labels[s] = s;
+        while (head < tail) {
+            const int64_t n = queue[head++];
+            int c[3];
+            coords(p, n, &c[0], &c[1], &c[2]);
+            for (int a = 0; a < 3; ++a) {
+                if (dims[a] == 1) continue;
+                for (int dir = -1; dir <= 1; dir += 2) {
+                    int q[3] = {c[0], c[1], c[2]};
+                    q[a] += dir;
+                    if (q[a] < 0 || q[a] >= dims[a]) {
+                        if (p->bc[a] != 0) continue;
+                        q[a] = (q[a] + dims[a]) % dims[a];
+                    }
+                    const int64_t m = idx(p, q[0], q[1], q[2]);
+                    if (phi[m] > 0.0 && labels[m] < 0) {
+                        labels[m] = s;
+                        queue[tail++] = m;
+                    }
+                }
+            }
+        }
+    }
+    free(queue); free(phi);
+    return count;
+}

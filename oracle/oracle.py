@@ -75,6 +75,14 @@ def lib():
         L.orc_run.argtypes = [pp, dp, ctypes.c_int64]
         L.orc_observables.argtypes = [pp, dp, dp]
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_phase_indicator.argtypes = [pp, dp, dp]
+        L.orc_interface_crossings.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
+                                              ctypes.c_int]
+        L.orc_interface_crossings.restype = ctypes.c_int
+        L.orc_plane_area.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int]
+        L.orc_plane_area.restype = ctypes.c_double
+        L.orc_label_components.argtypes = [pp, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_label_components.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -218,3 +226,34 @@ def set_threads(n: int) -> None:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def phase_indicator(p: dict, f: np.ndarray) -> np.ndarray:
+    """rho^N (two components) or rho - (rho0_R + rho0_B)/2 (SC multiphase), (nz, ny, nx)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros((p["nz"], p["ny"], p["nx"]))
+    lib().orc_phase_indicator(ctypes.byref(_struct(p)), _ptr(f), _ptr(out))
+    return out
+
+
+def interface_crossings(p: dict, f: np.ndarray, axis: int, c1: int, c2: int, max_out: int = 64):
+    """Interpolated interface positions along a lattice line (ascending)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(max_out)
+    n = lib().orc_interface_crossings(ctypes.byref(_struct(p)), _ptr(f), axis, c1, c2, _ptr(out),
+                                      max_out)
+    return out[:min(n, max_out)].copy(), n
+
+
+def plane_area(p: dict, f: np.ndarray, axis: int, pos: int) -> float:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return float(lib().orc_plane_area(ctypes.byref(_struct(p)), _ptr(f), axis, pos))
+
+
+def label_components(p: dict, f: np.ndarray):
+    """(count, labels (nz, ny, nx) int64: smallest node index of the component, -1 outside)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    labels = np.zeros((p["nz"], p["ny"], p["nx"]), dtype=np.int64)
+    n = lib().orc_label_components(ctypes.byref(_struct(p)), _ptr(f),
+                                   labels.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return int(n), labels
