@@ -101,15 +101,20 @@ def test_unsupported_combinations(M):
     with pytest.raises(M.MclbmError) as e:
         M.state_bytes(M.make_params(lattice=M.D3Q19, model=M.SC_MP, Pi=0.01))
     assert e.value.status == -2
-    # fused needs D3Q19, no repulsion, nx % 32 == 0, FP32-family storage
+    # fused needs D3Q19, no repulsion, nx % 32 == 0 and ny % 4 == 0
     with pytest.raises(M.MclbmError) as e:
         M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, kernel=M.KERNEL_FUSED))
     assert e.value.status == -2
     with pytest.raises(M.MclbmError):
         M.state_bytes(M.make_params(lattice=M.D3Q19, nx=40, kernel=M.KERNEL_FUSED))
     with pytest.raises(M.MclbmError):
-        M.state_bytes(M.make_params(lattice=M.D3Q19, precision=M.FP64, kernel=M.KERNEL_FUSED))
-    assert M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=32, kernel=M.KERNEL_FUSED)) > 0
+        M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=18, precision=M.FP64,
+                                    kernel=M.KERNEL_FUSED))
+    with pytest.raises(M.MclbmError):
+        M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=32, Pi=0.01, kernel=M.KERNEL_FUSED))
+    for prec in (M.FP64, M.FP32, M.MIXED, M.FP16):
+        assert M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=32, precision=prec,
+                                           kernel=M.KERNEL_FUSED)) > 0
 
 
 def test_d2q9_rejects_z_boundaries(M):
