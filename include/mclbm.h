@@ -54,7 +54,7 @@ extern "C" {
 #endif
 
 #define MCLBM_VERSION_MAJOR 1
-#define MCLBM_VERSION_MINOR 1
+#define MCLBM_VERSION_MINOR 2
 #define MCLBM_ABI_VERSION 1
 
 typedef int32_t mclbm_status;
@@ -222,6 +222,38 @@ mclbm_status mclbm_restore(mclbm_sim *sim, const void *d_src, int64_t step);
 
 /* Read the device divergence flag (synchronises): 1 if set. */
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged);
+
+/* Interface observables.  The phase indicator of a node is rho^N =
+ * (rho_R - rho_B)/rho for the two-component models and rho - (rho0_R +
+ * rho0_B)/2 for SC multiphase (the interface definitions of the droplet-
+ * oscillation study), computed in FP64 from the stored populations; a node
+ * is inside the red (liquid) phase when it is > 0.  All three synchronise the
+ * stream; EINVAL on bad arguments, EDEVICE on a HIP error.
+ *
+ * mclbm_interface_crossings: along the lattice line parallel to `axis` (0 x,
+ * 1 y, 2 z) through the node whose other two coordinates are (c1, c2) in
+ * increasing axis order, the positions where the indicator changes side,
+ * each by linear interpolation between the two nodes of its segment (the
+ * radius and endpoint measurements of the oscillation and ligament
+ * studies), ascending; a periodic axis includes the segment from its last
+ * node to its first (position in [n-1, n)).  *count = number of crossings;
+ * the first min(count, max) positions go to host array h_pos.
+ *
+ * mclbm_plane_area: over the lattice plane `pos` normal to `axis`, the sum of
+ * the red fraction (1 + rho^N)/2, or for SC multiphase the number of nodes
+ * with rho >= (rho0_R + rho0_B)/2 (the bridge radius of the coalescence
+ * study is sqrt(area / pi)); deterministic.
+ *
+ * mclbm_droplets: connected components of the inside nodes under face
+ * adjacency, wrapping across periodic faces (droplet counting of the
+ * emulsion study).  *count = number of components; h_sizes receives the
+ * node counts of the largest min(count, max), in decreasing order.  The
+ * first call allocates 16 bytes per node of device scratch, kept until
+ * mclbm_destroy; EUNSUPPORTED for 2^31 - 2 nodes or more. */
+mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
+                                       int32_t max, int32_t *count);
+mclbm_status mclbm_plane_area(mclbm_sim *sim, int32_t axis, int32_t pos, double *area);
+mclbm_status mclbm_droplets(mclbm_sim *sim, int32_t max, int32_t *count, int64_t *h_sizes);
 
 /* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass:
  * D3Q19 without the repulsion force, nx % 32 == 0 and ny % 4 == 0) or

@@ -102,6 +102,12 @@ def lib():
             "mclbm_restore": [_vp, _vp, ctypes.c_int64],
             "mclbm_diverged": [_vp, ctypes.POINTER(ctypes.c_int32)],
             "mclbm_kernel_used": [_vp, ctypes.POINTER(ctypes.c_int32)],
+            "mclbm_interface_crossings": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)],
+            "mclbm_plane_area": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+            "mclbm_droplets": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int64)],
             "mclbm_batch_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                    _vp, ctypes.POINTER(_vp)],
             "mclbm_batch_step": [_vp, ctypes.c_int32, ctypes.c_int32],
@@ -308,6 +314,27 @@ class Sim:
         d = ctypes.c_int32()
         _check(lib().mclbm_diverged(self._h, ctypes.byref(d)), "mclbm_diverged")
         return bool(d.value)
+
+    def interface_crossings(self, axis: int, c1: int, c2: int, max_out: int = 64):
+        """Interpolated interface positions along the lattice line parallel to
+        `axis` through (c1, c2) (the other coordinates, in axis order), ascending."""
+        out = (ctypes.c_double * max(1, max_out))()
+        n = ctypes.c_int32()
+        _check(lib().mclbm_interface_crossings(self._h, axis, c1, c2, out, max_out, ctypes.byref(n)),
+               "mclbm_interface_crossings")
+        return [out[i] for i in range(min(n.value, max_out))], n.value
+
+    def plane_area(self, axis: int, pos: int) -> float:
+        a = ctypes.c_double()
+        _check(lib().mclbm_plane_area(self._h, axis, pos, ctypes.byref(a)), "mclbm_plane_area")
+        return a.value
+
+    def droplets(self, max_out: int = 1024):
+        """(number of face-connected inside regions, their node counts, largest first)."""
+        sizes = (ctypes.c_int64 * max(1, max_out))()
+        n = ctypes.c_int32()
+        _check(lib().mclbm_droplets(self._h, max_out, ctypes.byref(n), sizes), "mclbm_droplets")
+        return n.value, [sizes[i] for i in range(min(n.value, max_out))]
 
     def kernel_used(self) -> int:
         """KERNEL_FUSED or KERNEL_TWO_PASS: the step kernel this simulation runs."""

@@ -242,6 +242,136 @@ __global__ void kb_advance(SimDesc *D, int nsims)
     else if (d.steps >= d.target) d.state = 1;
 }
 
+// ---------------------------------------------------------------------------
+// Interface observables (precision-independent parts).
+// ---------------------------------------------------------------------------
+// Sign changes of the phase indicator along a sampled line, each placed by
+// linear interpolation between its two nodes, in ascending order (one block:
+// contiguous chunks of segments per thread, offsets by a prefix sum).
+__global__ __launch_bounds__(256) void k_crossings(const double *__restrict__ line, int len, int periodic, int max,
+                                                   double *__restrict__ out, int *__restrict__ count)
+{
+    __shared__ int off[257];
+    const int segs = periodic && len > 1 ? len : len - 1;
+    const int per = (segs + 255) / 256;
+    const int t = threadIdx.x;
+    const int s0 = t * per, s1 = min(segs, s0 + per);
+    int c = 0;
+    for (int s = s0; s < s1; ++s) {
+        const double a = line[s], b = line[(s + 1) % len];
+        if ((a > 0.0) != (b > 0.0)) ++c;
+    }
+    off[t + 1] = c;
+    if (t == 0) off[0] = 0;
+    __syncthreads();
+    if (t == 0)
+        for (int i = 1; i <= 256; ++i) off[i] += off[i - 1];
+    __syncthreads();
+    int k = off[t];
+    for (int s = s0; s < s1; ++s) {
+        const double a = line[s], b = line[(s + 1) % len];
+        if ((a > 0.0) != (b > 0.0)) {
+            if (k < max) out[k] = s + a / (a - b);
+            ++k;
+        }
+    }
+    if (t == 0) *count = off[256];
+}
+
+// Sum of per-block partials in a fixed order (one block).
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ partials, int n,
+                                                      double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < n; b += 256) v += partials[b];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void k_fill_int(int *__restrict__ a, long long n, int v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// Connected components of the inside nodes under face adjacency (periodic
+// axes wrap), by alternating launches of min-label propagation and pointer
+// jumping.  A label is always the index of a node of the same component and
+// never increases; when neither pass changes anything, every node carries
+// the smallest index of its component.  Each label has a single writer (its
+// own node); a neighbour's label read during an update is its old or new
+// value, both valid.
+__device__ __forceinline__ long long face_neighbour(const KParams &P, int x, int y, int z, int axis, int dir)
+{
+    int c[3] = {x, y, z};
+    const int d[3] = {P.nx, P.ny, P.nz};
+    if (d[axis] == 1) return -1;
+    c[axis] += dir;
+    if (c[axis] < 0 || c[axis] >= d[axis]) {
+        if (P.bc[axis] != 0) return -1;
+        c[axis] = c[axis] < 0 ? c[axis] + d[axis] : c[axis] - d[axis];
+    }
+    return (long long)c[0] + (long long)P.nx * ((long long)c[1] + (long long)P.ny * c[2]);
+}
+
+__global__ __launch_bounds__(256) void k_ccl_prop(KParams P, int *__restrict__ lab, unsigned *__restrict__ changed)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= P.N) return;
+    const int l = lab[n];
+    if (l < 0) return;
+    const int x = (int)(n % P.nx), y = (int)((n / P.nx) % P.ny), z = (int)(n / ((long long)P.nx * P.ny));
+    int m = l;
+    for (int a = 0; a < 3; ++a)
+        for (int dir = -1; dir <= 1; dir += 2) {
+            const long long q = face_neighbour(P, x, y, z, a, dir);
+            if (q < 0) continue;
+            const int v = lab[q];
+            if (v >= 0 && v < m) m = v;
+        }
+    if (m < l) {
+        lab[n] = m;
+        atomicOr(changed, 1u);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ccl_jump(long long N, int *__restrict__ lab, unsigned *__restrict__ changed)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int l = lab[n];
+    if (l < 0) return;
+    const int ll = lab[l];
+    if (ll < l) {
+        lab[n] = ll;
+        atomicOr(changed, 1u);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ccl_sizes(long long N, const int *__restrict__ lab, int *__restrict__ sizes)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N && lab[n] >= 0) atomicAdd(&sizes[lab[n]], 1);
+}
+
+// (root, size) pairs of the components, in any order (sorted on the host).
+__global__ __launch_bounds__(256) void k_ccl_roots(long long N, const int *__restrict__ lab,
+                                                   const int *__restrict__ sizes, int *__restrict__ pairs,
+                                                   int *__restrict__ nroots)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || lab[n] != (int)n) return;
+    const int k = atomicAdd(nroots, 1);
+    pairs[2 * k] = (int)n;
+    pairs[2 * k + 1] = sizes[n];
+}
+
 }  // namespace mclbm
 
 struct mclbm_sim {
@@ -264,6 +394,8 @@ struct mclbm_sim {
     double *d_obs;
     double *h_obs;
     unsigned *h_flag;
+    double *d_iface;   // interface observables: sampled line and outputs (lazy)
+    int *d_lab;        // component labels, sizes, root pairs and count: 4 N + 64 ints (lazy)
 };
 
 struct mclbm_batch {
@@ -434,6 +566,8 @@ mclbm_status mclbm_destroy(mclbm_sim *sim)
     if (sim->d_obs) (void)hipFree(sim->d_obs);
     if (sim->h_obs) (void)hipHostFree(sim->h_obs);
     if (sim->h_flag) (void)hipHostFree(sim->h_flag);
+    if (sim->d_iface) (void)hipFree(sim->d_iface);
+    if (sim->d_lab) (void)hipFree(sim->d_lab);
     delete sim;
     return MCLBM_OK;
 }
@@ -769,3 +903,128 @@ mclbm_status mclbm_batch_status(mclbm_batch *b, int32_t *status, int64_t *steps)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Interface observables
+// ---------------------------------------------------------------------------
+static int axis_len(const mclbm_sim *sim, int a) { return a == 0 ? sim->prm.nx : (a == 1 ? sim->prm.ny : sim->prm.nz); }
+
+static mclbm_status iface_buffers(mclbm_sim *sim)
+{
+    if (sim->d_iface) return MCLBM_OK;
+    const int mx = std::max(sim->prm.nx, std::max(sim->prm.ny, sim->prm.nz));
+    MCLBM_HIP(hipMalloc((void **)&sim->d_iface, sizeof(double) * (2 * (size_t)mx + 16)));
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
+                                       int32_t max, int32_t *count)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (axis < 0 || axis > 2) return fail(MCLBM_EINVAL, "axis %d", axis);
+    if (!count || max < 0 || (max > 0 && !h_pos)) return fail(MCLBM_EINVAL, "bad output arguments");
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    if (c1 < 0 || c1 >= axis_len(sim, a1) || c2 < 0 || c2 >= axis_len(sim, a2))
+        return fail(MCLBM_EINVAL, "line (%d, %d) outside the box", c1, c2);
+    s = iface_buffers(sim);
+    if (s) return s;
+    const long long nx = sim->prm.nx, sxy = nx * sim->prm.ny;
+    const long long stride[3] = {1, nx, sxy};
+    const int len = axis_len(sim, axis);
+    NodeSet ns;
+    ns.base = (long long)c1 * stride[a1] + (long long)c2 * stride[a2];
+    ns.s1 = stride[axis];
+    ns.s2 = 0;
+    ns.len1 = len;
+    ns.count = len;
+    double *line = sim->d_iface, *out = sim->d_iface + len + 8;
+    int *d_count = (int *)(sim->d_iface + 2 * len + 8);
+    const int keep = std::min(max, len);
+    sim->ops->phase_sample(sim->kp, sim->f[sim->cur], ns, line, sim->stream);
+    hipLaunchKernelGGL(k_crossings, dim3(1), dim3(256), 0, sim->stream, line, len,
+                       sim->prm.bc[axis] == MCLBM_PERIODIC ? 1 : 0, keep, out, d_count);
+    s = launched("interface_crossings");
+    if (s) return s;
+    int n = 0;
+    MCLBM_HIP(hipMemcpyAsync(&n, d_count, sizeof(int), hipMemcpyDeviceToHost, sim->stream));
+    MCLBM_HIP(hipStreamSynchronize(sim->stream));
+    if (keep > 0 && n > 0)
+        MCLBM_HIP(hipMemcpy(h_pos, out, sizeof(double) * (size_t)std::min(n, keep), hipMemcpyDeviceToHost));
+    *count = n;
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_plane_area(mclbm_sim *sim, int32_t axis, int32_t pos, double *area)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (axis < 0 || axis > 2) return fail(MCLBM_EINVAL, "axis %d", axis);
+    if (!area) return fail(MCLBM_EINVAL, "area is NULL");
+    if (pos < 0 || pos >= axis_len(sim, axis)) return fail(MCLBM_EINVAL, "plane %d outside the box", pos);
+    const long long nx = sim->prm.nx, ny = sim->prm.ny, nz = sim->prm.nz, sxy = nx * ny;
+    NodeSet ns;
+    if (axis == 0) { ns.base = pos; ns.s1 = nx; ns.len1 = ny; ns.s2 = sxy; ns.count = ny * nz; }
+    else if (axis == 1) { ns.base = (long long)pos * nx; ns.s1 = 1; ns.len1 = nx; ns.s2 = sxy; ns.count = nx * nz; }
+    else { ns.base = (long long)pos * sxy; ns.s1 = 1; ns.len1 = nx; ns.s2 = nx; ns.count = nx * ny; }
+    const int nb = (int)std::min<long long>(kRedBlocks, grid_of(ns.count));
+    sim->ops->phase_area(sim->kp, sim->f[sim->cur], ns, sim->d_partials, nb, sim->stream);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, sim->stream, sim->d_partials, nb, sim->d_obs);
+    s = launched("plane_area");
+    if (s) return s;
+    MCLBM_HIP(hipMemcpyAsync(sim->h_obs, sim->d_obs, sizeof(double), hipMemcpyDeviceToHost, sim->stream));
+    MCLBM_HIP(hipStreamSynchronize(sim->stream));
+    *area = sim->h_obs[0];
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_droplets(mclbm_sim *sim, int32_t max, int32_t *count, int64_t *h_sizes)
+{
+    mclbm_status s = check_sim(sim);
+    if (s) return s;
+    if (!count || max < 0 || (max > 0 && !h_sizes)) return fail(MCLBM_EINVAL, "bad output arguments");
+    const long long N = sim->kp.N;
+    if (N >= (1LL << 31) - 2) return fail(MCLBM_EUNSUPPORTED, "labelling needs fewer than 2^31 nodes");
+    // labels N, sizes N, (root, size) pairs 2 N (up to one component per
+    // node), the component count
+    if (!sim->d_lab) MCLBM_HIP(hipMalloc((void **)&sim->d_lab, sizeof(int) * (4 * (size_t)N + 64)));
+    int *lab = sim->d_lab, *sizes = lab + N, *pairs = lab + 2 * N, *d_n = lab + 4 * N;
+    const unsigned g = (unsigned)((N + 255) / 256);
+    sim->ops->phase_labels(sim->kp, sim->f[sim->cur], lab, sim->stream);
+    // each check runs four rounds; a round changes something until the
+    // labels have converged, and every change lowers some label
+    const long long max_checks = N / 4 + 16;
+    for (long long it = 0;; ++it) {
+        if (it > max_checks) return fail(MCLBM_EDEVICE, "labelling did not converge");
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, sim->stream, (int *)sim->d_flag + 1, 1LL, 0);
+        for (int r = 0; r < 4; ++r) {
+            hipLaunchKernelGGL(k_ccl_prop, dim3(g), dim3(256), 0, sim->stream, sim->kp, lab,
+                               (unsigned *)sim->d_flag + 1);
+            hipLaunchKernelGGL(k_ccl_jump, dim3(g), dim3(256), 0, sim->stream, N, lab, (unsigned *)sim->d_flag + 1);
+        }
+        s = launched("droplets");
+        if (s) return s;
+        MCLBM_HIP(hipMemcpyAsync(sim->h_flag, (unsigned *)sim->d_flag + 1, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                 sim->stream));
+        MCLBM_HIP(hipStreamSynchronize(sim->stream));
+        if (*sim->h_flag == 0) break;
+    }
+    hipLaunchKernelGGL(k_fill_int, dim3(g), dim3(256), 0, sim->stream, sizes, N, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, sim->stream, d_n, 1LL, 0);
+    hipLaunchKernelGGL(k_ccl_sizes, dim3(g), dim3(256), 0, sim->stream, N, (const int *)lab, sizes);
+    hipLaunchKernelGGL(k_ccl_roots, dim3(g), dim3(256), 0, sim->stream, N, (const int *)lab, (const int *)sizes,
+                       pairs, d_n);
+    s = launched("droplets");
+    if (s) return s;
+    int n = 0;
+    MCLBM_HIP(hipMemcpyAsync(&n, d_n, sizeof(int), hipMemcpyDeviceToHost, sim->stream));
+    MCLBM_HIP(hipStreamSynchronize(sim->stream));
+    std::vector<int> hp(2 * (size_t)n);
+    if (n > 0) MCLBM_HIP(hipMemcpy(hp.data(), pairs, sizeof(int) * 2 * (size_t)n, hipMemcpyDeviceToHost));
+    std::vector<std::pair<int, int>> comp((size_t)n);
+    for (int i = 0; i < n; ++i) comp[(size_t)i] = {-hp[2 * (size_t)i + 1], hp[2 * (size_t)i]};
+    std::sort(comp.begin(), comp.end());   // largest first, then by smallest node index
+    for (int i = 0; i < std::min(n, (int)max); ++i) h_sizes[i] = -(int64_t)comp[(size_t)i].first;
+    *count = n;
+    return MCLBM_OK;
+}

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "interface.hpp"
 #include "launch.hpp"
 
 namespace mclbm {
@@ -27,6 +28,13 @@ struct Ops {
     // batched step pieces over a group of descriptors
     virtual void batch_step(SimDesc *D, int n, long long blocks, long long oblocks, bool any_outflow,
                             hipStream_t s) const = 0;
+    // interface observables: phase indicator of a node set, per-block red
+    // fraction partial sums over a node set, initial component labels
+    virtual void phase_sample(const KParams &P, const void *f, const NodeSet &ns, double *out,
+                              hipStream_t s) const = 0;
+    virtual void phase_area(const KParams &P, const void *f, const NodeSet &ns, double *partials, int nblocks,
+                            hipStream_t s) const = 0;
+    virtual void phase_labels(const KParams &P, const void *f, int *labels, hipStream_t s) const = 0;
 };
 
 inline unsigned grid_of(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -108,6 +116,23 @@ struct OpsT final : Ops {
     {
         hipLaunchKernelGGL((k_obs<L, PR, MODEL>), dim3(nblocks), dim3(kBlock), 0, s, P, (const S *)f,
                            (const FT *)field, e, partials);
+    }
+    void phase_sample(const KParams &P, const void *f, const NodeSet &ns, double *out,
+                      hipStream_t s) const override
+    {
+        hipLaunchKernelGGL((k_phase_sample<L, PR, MODEL>), dim3(grid_of(ns.count)), dim3(kBlock), 0, s, P,
+                           (const S *)f, ns, out);
+    }
+    void phase_area(const KParams &P, const void *f, const NodeSet &ns, double *partials, int nblocks,
+                    hipStream_t s) const override
+    {
+        hipLaunchKernelGGL((k_phase_area<L, PR, MODEL>), dim3(nblocks), dim3(kBlock), 0, s, P, (const S *)f, ns,
+                           partials);
+    }
+    void phase_labels(const KParams &P, const void *f, int *labels, hipStream_t s) const override
+    {
+        hipLaunchKernelGGL((k_phase_labels<L, PR, MODEL>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
+                           (const S *)f, labels);
     }
     void batch_step(SimDesc *D, int n, long long blocks, long long oblocks, bool any_outflow,
                     hipStream_t s) const override

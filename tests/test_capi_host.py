@@ -34,7 +34,7 @@ def test_library_exports_every_declared_function(M):
 
 
 def test_version_and_status_strings(M):
-    assert M.version() == (1, 1)
+    assert M.version() == (1, 2)
     L = M.lib()
     for s in (0, 1, -1, -2, -3, -4):
         assert L.mclbm_status_str(s)
@@ -133,3 +133,16 @@ def test_single_hip_runtime_when_library_loads_first():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def test_interface_observables_reject_bad_arguments_without_a_device(M):
+    """The interface observables validate their arguments on the host (no
+    device work): NULL simulation -> EINVAL."""
+    L = M.lib()
+    n = ctypes.c_int32()
+    a = ctypes.c_double()
+    sizes = (ctypes.c_int64 * 4)()
+    pos = (ctypes.c_double * 4)()
+    assert L.mclbm_interface_crossings(None, 0, 0, 0, pos, 4, ctypes.byref(n)) == -1
+    assert L.mclbm_plane_area(None, 0, 0, ctypes.byref(a)) == -1
+    assert L.mclbm_droplets(None, 4, ctypes.byref(n), sizes) == -1
