@@ -54,6 +54,8 @@ typedef struct {
     double rho0_X;         /* reference density in the SC cross force       */
     double Pi;             /* CG repulsion magnitude (0 = off)              */
     double chi;            /* CG repulsion exponent                          */
+    double Ga_R, Ga_B;     /* SC two-component attraction couplings (belt 1)  */
+    double Gr_R, Gr_B;     /* SC two-component repulsion couplings (belts 1+2) */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -468,11 +470,64 @@ static void scmp_force_at(const orc_params *p, const orc_lattice *L, const doubl
     for (int d = 0; d < 3; ++d) F[d] = -p->G * psi[n] * s[d];
 }
 
-/* Cross-component force on each colour (Eq. doublebeltrepulsionforce2 over
- * belt 1 = nearest neighbours):
- *   F_s = -(G_RB / rho_0^2) rho_s(x) sum_i w_i rho_s'(x + c_i) c_i. */
+/* The multirange neighbourhood of the two-component Shan-Chen forces
+ * (Eq. pweights): the 92 vectors c in {-2..2}^3 with |c|^2 in {1, 2, 3, 4,
+ * 5, 6, 8}; belt 1 is |c|^2 <= 2 (the D3Q19 set), belt 2 the rest.  Weights
+ * by shell: p = 4/135, 1/63, 2/315, 5/1512, 1/945, 1/1890, 1/15120 for
+ * |c|^2 = 1, 2, 3, 4, 5, 6, 8 (p = 0 for the rest vector); w is the D3Q19
+ * lattice weight on belt 1 (1/18, 1/36) and 0 on belt 2.  Enumerated with x
+ * fastest, then y, then z. */
+typedef struct {
+    int n;
+    int c[92][3];
+    double p[92], w[92];
+} orc_belts;
+
+static void belts(orc_belts *B)
+{
+    B->n = 0;
+    for (int cz = -2; cz <= 2; ++cz)
+        for (int cy = -2; cy <= 2; ++cy)
+            for (int cx = -2; cx <= 2; ++cx) {
+                const int r2 = cx * cx + cy * cy + cz * cz;
+                double p = 0.0, w = 0.0;
+                switch (r2) {
+                case 1: p = 4.0 / 135.0; w = 1.0 / 18.0; break;
+                case 2: p = 1.0 / 63.0; w = 1.0 / 36.0; break;
+                case 3: p = 2.0 / 315.0; break;
+                case 4: p = 5.0 / 1512.0; break;
+                case 5: p = 1.0 / 945.0; break;
+                case 6: p = 1.0 / 1890.0; break;
+                case 8: p = 1.0 / 15120.0; break;
+                default: continue;   /* rest vector, |c|^2 = 9, 12 */
+                }
+                B->c[B->n][0] = cx; B->c[B->n][1] = cy; B->c[B->n][2] = cz;
+                B->p[B->n] = p;
+                B->w[B->n] = w;
+                ++B->n;
+            }
+}
+
+static int multirange_on(const orc_params *p)
+{
+    return p->Ga_R != 0.0 || p->Ga_B != 0.0 || p->Gr_R != 0.0 || p->Gr_B != 0.0;
+}
+
+/* Forces on each colour of the two-component Shan-Chen model
+ * (Eq. benziforces): the cross-component repulsion (Eq.
+ * doublebeltrepulsionforce2, belt 1)
+ *   F^X_s = -(G_RB / rho_0^2) rho_s(x) sum_i w_i rho_s'(x + c_i) c_i,
+ * plus, when a multirange coupling is set, the attraction on belt 1 (Eq.
+ * doublebeltattractiveforce) and the repulsion on belts 1 and 2 (Eq.
+ * doublebeltrepulsionforce)
+ *   F^a_s = -G^a_s psi_s(x) sum_{belt 1} w_i psi_s(x + c_i) c_i,
+ *   F^r_s = -G^r_s psi_s(x) sum_{belts 1,2} p_i psi_s(x + c_i) c_i,
+ * with psi_s = rho_0 (1 - exp(-rho_s / rho_0)) (Eq. pseudopotential; reading:
+ * the same psi for both species, rho_0 = psi_rho0).  psiR/psiB may be NULL
+ * when no multirange coupling is set. */
 static void scmc_forces_at(const orc_params *p, const orc_lattice *L, const double *rhoR,
-                           const double *rhoB, int64_t n, double FR[3], double FB[3])
+                           const double *rhoB, const double *psiR, const double *psiB,
+                           int64_t n, double FR[3], double FB[3])
 {
     int x, y, z;
     coords(p, n, &x, &y, &z);
@@ -488,6 +543,23 @@ static void scmc_forces_at(const orc_params *p, const orc_lattice *L, const doub
     for (int d = 0; d < 3; ++d) {
         FR[d] = -pref * rhoR[n] * sB[d];
         FB[d] = -pref * rhoB[n] * sR[d];
+    }
+    if (!multirange_on(p)) return;
+    orc_belts B;
+    belts(&B);
+    double aR[3] = {0, 0, 0}, aB[3] = {0, 0, 0}, rR[3] = {0, 0, 0}, rB[3] = {0, 0, 0};
+    for (int b = 0; b < B.n; ++b) {
+        int64_t m = stencil_node(p, x, y, z, B.c[b][0], B.c[b][1], B.c[b][2]);
+        for (int d = 0; d < 3; ++d) {
+            aR[d] += B.w[b] * psiR[m] * B.c[b][d];
+            aB[d] += B.w[b] * psiB[m] * B.c[b][d];
+            rR[d] += B.p[b] * psiR[m] * B.c[b][d];
+            rB[d] += B.p[b] * psiB[m] * B.c[b][d];
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        FR[d] += -p->Ga_R * psiR[n] * aR[d] - p->Gr_R * psiR[n] * rR[d];
+        FB[d] += -p->Ga_B * psiB[n] * aB[d] - p->Gr_B * psiB[n] * rB[d];
     }
 }
 
@@ -524,11 +596,19 @@ static void scmc_collide_pass(const orc_params *p, const orc_lattice *L, const d
     const int64_t N = nnodes(p);
     const int Q = L->Q;
     const double om[2] = {1.0 / p->tau_R, 1.0 / p->tau_B};
+    /* psi of both species for the multirange forces (gR / gB scratch) */
+    double *psiR = NULL, *psiB = NULL;
+    if (multirange_on(p)) {
+        psiR = w->gR;
+        psiB = w->gB;
+        psi_pass(p, w->rhoR, psiR, N);
+        psi_pass(p, w->rhoB, psiB, N);
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) {
         double rk[2] = {w->rhoR[n], w->rhoB[n]};
         double Fk[2][3], u[3];
-        scmc_forces_at(p, L, w->rhoR, w->rhoB, n, Fk[0], Fk[1]);
+        scmc_forces_at(p, L, w->rhoR, w->rhoB, psiR, psiB, n, Fk[0], Fk[1]);
         for (int d = 0; d < 3; ++d)
             u[d] = (w->j[d * N + n] + 0.5 * (Fk[0][d] + Fk[1][d])) / (rk[0] + rk[1]);
         for (int k = 0; k < 2; ++k)
@@ -829,8 +909,10 @@ void orc_observables(const orc_params *p, const double *f, double *out)
     double *rB = calloc((size_t)N, sizeof(double));
     double *j = calloc((size_t)(3 * N), sizeof(double));
     double *psi = calloc((size_t)N, sizeof(double));
+    double *psiB = calloc((size_t)N, sizeof(double));
     moments_pass(p, &L, f, rR, rB, j);
-    if (p->model == 1) psi_pass(p, rR, psi, N);
+    if (p->model == 1 || (p->model == 2 && multirange_on(p))) psi_pass(p, rR, psi, N);
+    if (p->model == 2 && multirange_on(p)) psi_pass(p, rB, psiB, N);
     double mR = 0, mB = 0, mom[3] = {0, 0, 0}, ek = 0, umax = 0, vol = 0;
     double sin_[10] = {0}, sout[10] = {0};
     double cin[10] = {0}, cout_[10] = {0};
@@ -844,7 +926,7 @@ void orc_observables(const orc_params *p, const double *f, double *out)
             scmp_force_at(p, &L, psi, n, F);
         } else if (p->model == 2) {
             double FR[3], FB[3];
-            scmc_forces_at(p, &L, rR, rB, n, FR, FB);
+            scmc_forces_at(p, &L, rR, rB, psi, psiB, n, FR, FB);
             for (int d = 0; d < 3; ++d) F[d] = FR[d] + FB[d];
         }
         double uu[3];
@@ -895,7 +977,7 @@ void orc_observables(const orc_params *p, const double *f, double *out)
     out[0] = mR; out[1] = mB; out[2] = mom[0]; out[3] = mom[1]; out[4] = mom[2];
     out[5] = ek; out[6] = umax; out[7] = rho_in; out[8] = rho_out; out[9] = eps_used;
     out[10] = vol; out[11] = nin; out[12] = nout; out[13] = diverged;
-    free(rR); free(rB); free(j); free(psi);
+    free(rR); free(rB); free(j); free(psi); free(psiB);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1032,4 +1114,45 @@ int64_t orc_label_components(const orc_params *p, const double *f, int64_t *labe
     }
     free(queue); free(phi);
     return count;
+}
+
+/* The multirange neighbourhood as tables: c[3*b + d], p[b], w[b]; returns the
+ * number of vectors (92). */
+int orc_belts_table(int32_t *c, double *p, double *w)
+{
+    orc_belts B;
+    belts(&B);
+    for (int b = 0; b < B.n; ++b) {
+        for (int d = 0; d < 3; ++d) c[3 * b + d] = B.c[b][d];
+        p[b] = B.p[b];
+        w[b] = B.w[b];
+    }
+    return B.n;
+}
+
+/* Per-node forces of the two-component Shan-Chen model on the state f:
+ * FR[d*N + n], FB[d*N + n] (cross repulsion plus, when set, the multirange
+ * attraction and repulsion). */
+void orc_sc_forces(const orc_params *p, const double *f, double *FR, double *FB)
+{
+    orc_lattice L;
+    get_lattice(p->lattice, &L);
+    const int64_t N = nnodes(p);
+    double *rR = calloc((size_t)N, sizeof(double));
+    double *rB = calloc((size_t)N, sizeof(double));
+    double *j = calloc((size_t)(3 * N), sizeof(double));
+    double *psR = calloc((size_t)N, sizeof(double));
+    double *psB = calloc((size_t)N, sizeof(double));
+    moments_pass(p, &L, f, rR, rB, j);
+    psi_pass(p, rR, psR, N);
+    psi_pass(p, rB, psB, N);
+    for (int64_t n = 0; n < N; ++n) {
+        double a[3], b[3];
+        scmc_forces_at(p, &L, rR, rB, psR, psB, n, a, b);
+        for (int d = 0; d < 3; ++d) {
+            FR[d * N + n] = a[d];
+            FB[d * N + n] = b[d];
+        }
+    }
+    free(rR); free(rB); free(j); free(psR); free(psB);
 }

@@ -43,13 +43,15 @@ class Params(ctypes.Structure):
         ("g_min", ctypes.c_double), ("G", ctypes.c_double), ("psi_rho0", ctypes.c_double),
         ("G_RB", ctypes.c_double), ("rho0_X", ctypes.c_double),
         ("Pi", ctypes.c_double), ("chi", ctypes.c_double),
+        ("Ga_R", ctypes.c_double), ("Ga_B", ctypes.c_double),
+        ("Gr_R", ctypes.c_double), ("Gr_B", ctypes.c_double),
     ]
 
 
 DEFAULTS = dict(lattice=1, model=0, nx=8, ny=8, nz=8, bc=(0, 0, 0), enhanced_eq=1,
                 rho0_R=1.0, rho0_B=1.0, tau_R=1.0, tau_B=1.0, A=0.01, beta=0.7,
                 alpha_B=0.2, g_min=1e-8, G=0.0, psi_rho0=1.0, G_RB=0.0, rho0_X=1.0,
-                Pi=0.0, chi=1.0)
+                Pi=0.0, chi=1.0, Ga_R=0.0, Ga_B=0.0, Gr_R=0.0, Gr_B=0.0)
 
 _lib = None
 
@@ -83,6 +85,9 @@ def lib():
         L.orc_plane_area.restype = ctypes.c_double
         L.orc_label_components.argtypes = [pp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.orc_label_components.restype = ctypes.c_int64
+        L.orc_belts_table.argtypes = [ctypes.POINTER(ctypes.c_int32), dp, dp]
+        L.orc_belts_table.restype = ctypes.c_int
+        L.orc_sc_forces.argtypes = [pp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -257,3 +262,21 @@ def label_components(p: dict, f: np.ndarray):
     n = lib().orc_label_components(ctypes.byref(_struct(p)), _ptr(f),
                                    labels.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return int(n), labels
+
+
+def belts_table():
+    """The multirange neighbourhood: (c (n, 3) int, p (n,), w (n,))."""
+    c = np.zeros((92, 3), dtype=np.int32)
+    p = np.zeros(92)
+    w = np.zeros(92)
+    n = lib().orc_belts_table(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(p), _ptr(w))
+    return c[:n].copy(), p[:n].copy(), w[:n].copy()
+
+
+def sc_forces(p: dict, f: np.ndarray):
+    """Two-component Shan-Chen forces on each colour, (3, nz, ny, nx) each."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    shape = (3, p["nz"], p["ny"], p["nx"])
+    FR, FB = np.zeros(shape), np.zeros(shape)
+    lib().orc_sc_forces(ctypes.byref(_struct(p)), _ptr(f), _ptr(FR), _ptr(FB))
+    return FR, FB
