@@ -53,9 +53,9 @@
 extern "C" {
 #endif
 
-#define MCLBM_VERSION_MAJOR 1
-#define MCLBM_VERSION_MINOR 2
-#define MCLBM_ABI_VERSION 1
+#define MCLBM_VERSION_MAJOR 2
+#define MCLBM_VERSION_MINOR 0
+#define MCLBM_ABI_VERSION 2
 
 typedef int32_t mclbm_status;
 #define MCLBM_OK 0
@@ -119,6 +119,15 @@ typedef struct mclbm_params {
     double rho0_X;        /* SC_MC reference density rho_0^(s) in the cross force   */
     double Pi;            /* CG repulsion magnitude (Eq. repForce); 0 = off         */
     double chi;           /* CG repulsion exponent, psi_rep = (1 - |rho^N|)^chi     */
+    /* SC_MC multirange couplings (Eq. benziforces): attraction on belt 1     */
+    /* (Eq. doublebeltattractiveforce) and repulsion on belts 1 and 2 (Eq.    */
+    /* doublebeltrepulsionforce, weights of Eq. pweights), per species, with  */
+    /* psi_s = psi_rho0 (1 - exp(-rho_s / psi_rho0)).  All zero = off; any    */
+    /* non-zero needs model SC_MC (EINVAL otherwise) and D3Q19 (EUNSUPPORTED  */
+    /* on D2Q9), and runs the two-pass kernels (the stencil reaches two       */
+    /* nodes).                                                               */
+    double Ga_R, Ga_B;    /* attraction couplings G^a of red and blue               */
+    double Gr_R, Gr_B;    /* repulsion couplings G^r of red and blue                */
 } mclbm_params;
 
 /* Observables (reductions over the whole lattice, FP64 accumulation in a

@@ -29,7 +29,7 @@ FP64, FP32, MIXED, FP16 = 0, 1, 2, 3
 PERIODIC, WALL, OUTFLOW = 0, 1, 2
 KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED = 0, 1, 2
 RUNNING, DONE, STOPPED_DIVERGED = 0, 1, 2
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class MclbmError(RuntimeError):
@@ -49,6 +49,8 @@ class Params(ctypes.Structure):
         ("alpha_B", ctypes.c_double), ("g_min", ctypes.c_double), ("G", ctypes.c_double),
         ("psi_rho0", ctypes.c_double), ("G_RB", ctypes.c_double), ("rho0_X", ctypes.c_double),
         ("Pi", ctypes.c_double), ("chi", ctypes.c_double),
+        ("Ga_R", ctypes.c_double), ("Ga_B", ctypes.c_double),
+        ("Gr_R", ctypes.c_double), ("Gr_B", ctypes.c_double),
     ]
 
 

@@ -214,8 +214,54 @@ __device__ __forceinline__ bool density_body(const KParams &P, const typename Pr
     } else {
         field[n] = (FT)dr[0];
         field[P.N + n] = (FT)dr[1];
+        if (P.multirange) {
+            field[2 * P.N + n] = (FT)pseudo_potential(H, H.rho0[0] + dr[0]);
+            field[3 * P.N + n] = (FT)pseudo_potential(H, H.rho0[1] + dr[1]);
+        }
     }
     return node_bad(r, j[0] + j[1] + j[2]);
+}
+
+// Multirange forces of the two-component Shan-Chen model added to FR, FB
+// (Eqs. doublebeltattractiveforce, doublebeltrepulsionforce):
+//   F^a_s = -G^a_s psi_s(x) sum_{belt 1} w_i psi_s(x + c_i) c_i,
+//   F^r_s = -G^r_s psi_s(x) sum_{belts 1, 2} p_i psi_s(x + c_i) c_i,
+// from the psi fields of the density pass (field + 2N red, + 3N blue), the
+// sums taken over the pairs (c, -c) of the belt table.
+// (the belt table as device constant data: the pair loop stays rolled, so the
+// kernels that carry this branch keep the register budget of the plain model)
+static __constant__ BeltTable kBeltTab = make_belt_table();
+
+template <class T, class FT>
+__device__ __forceinline__ void add_multirange(const KParams &P, const FT *__restrict__ field, int x, int y, int z,
+                                               long long n, T (&FR)[3], T (&FB)[3])
+{
+    const FT *psR = field + 2 * P.N, *psB = field + 3 * P.N;
+    T aR[3] = {T(0), T(0), T(0)}, aB[3] = {T(0), T(0), T(0)};
+    T rR[3] = {T(0), T(0), T(0)}, rB[3] = {T(0), T(0), T(0)};
+#pragma unroll 1
+    for (int b = 0; b < Belts::n; ++b) {
+        const int cc[3] = {kBeltTab.c[b][0], kBeltTab.c[b][1], kBeltTab.c[b][2]};
+        const long long mp = stencil_at(P, x, y, z, cc[0], cc[1], cc[2]);
+        const long long mm = stencil_at(P, x, y, z, -cc[0], -cc[1], -cc[2]);
+        const T dR = (T)psR[mp] - (T)psR[mm];
+        const T dB = (T)psB[mp] - (T)psB[mm];
+        const T wb = (T)kBeltTab.w[b], pb = (T)kBeltTab.p[b];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T cd = (T)cc[d];
+            aR[d] += wb * dR * cd;
+            aB[d] += wb * dB * cd;
+            rR[d] += pb * dR * cd;
+            rB[d] += pb * dB * cd;
+        }
+    }
+    const T pR = (T)psR[n], pB = (T)psB[n];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        FR[d] += -(T)P.Ga[0] * pR * aR[d] - (T)P.Gr[0] * pR * rR[d];
+        FB[d] += -(T)P.Ga[1] * pB * aB[d] - (T)P.Gr[1] * pB * rB[d];
+    }
 }
 
 // Gradient field of rho^N (repulsion variant): 3 sum w rho^N(x + c) c.
@@ -344,8 +390,10 @@ __device__ __forceinline__ void collide_body(const KParams &P, const typename Pr
         for (int d = 0; d < 3; ++d) {
             FR[d] = -H.xpref * (C)rR * sB[d];
             FB[d] = -H.xpref * (C)rB * sR[d];
-            u[d] = (C)((j[d] + M(0.5) * ((M)FR[d] + (M)FB[d])) * ir);
         }
+        if (P.multirange) add_multirange<C>(P, field, x, y, z, n, FR, FB);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] = (C)((j[d] + M(0.5) * ((M)FR[d] + (M)FB[d])) * ir);
         sc_collide_component<L, C, M>(g[0], H.om[0], dr[0], rR, u, FR, H.rho0[0], H.corrM[0], H.shiftM[0]);
         sc_collide_component<L, C, M>(g[1], H.om[1], dr[1], rB, u, FB, H.rho0[1], H.corrM[1], H.shiftM[1]);
     }
@@ -490,6 +538,11 @@ __device__ __forceinline__ bool node_state64(const KParams &P, const typename Pr
             stencil_sum<L>(vR, sR);
             stencil_sum<L>(vB, sB);
             for (int d = 0; d < 3; ++d) F[d] = -P.xpref * (rR * sB[d] + rB * sR[d]);
+            if (P.multirange) {
+                double FR[3] = {0.0, 0.0, 0.0}, FB[3] = {0.0, 0.0, 0.0};
+                add_multirange<double>(P, field, x, y, z, n, FR, FB);
+                for (int d = 0; d < 3; ++d) F[d] += FR[d] + FB[d];
+            }
         }
     }
     for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * F[d]) / r;

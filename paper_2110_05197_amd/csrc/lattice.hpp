@@ -49,4 +49,51 @@ struct D3Q19 {
     static constexpr double inv_len[3] = {0.0, 1.0, 0.70710678118654752440};
 };
 
+// Multirange neighbourhood of the two-component Shan-Chen forces (Eq.
+// pweights): the vectors of {-2..2}^3 with |c|^2 in {1, 2, 3, 4, 5, 6, 8}
+// (92 of them; belt 1 is |c|^2 <= 2, the D3Q19 set).  Both weights are even
+// in c, so the table keeps one vector of each pair (c, -c) -- the one whose
+// last non-zero component is positive -- and a force sum over the
+// neighbourhood is taken pairwise, sum_b weight_b (X(x + c_b) - X(x - c_b)) c_b.
+// p_b by shell: 4/135, 1/63, 2/315, 5/1512, 1/945, 1/1890, 1/15120;
+// w_b: the D3Q19 weight on belt 1 (1/18, 1/36), zero on belt 2.
+struct BeltTable {
+    int c[46][3];
+    double p[46];
+    double w[46];
+};
+
+constexpr double belt_weight_p(int r2)
+{
+    return r2 == 1 ? 4.0 / 135.0 : r2 == 2 ? 1.0 / 63.0 : r2 == 3 ? 2.0 / 315.0 : r2 == 4 ? 5.0 / 1512.0
+         : r2 == 5 ? 1.0 / 945.0 : r2 == 6 ? 1.0 / 1890.0 : r2 == 8 ? 1.0 / 15120.0 : 0.0;
+}
+
+constexpr BeltTable make_belt_table()
+{
+    BeltTable T{};
+    int k = 0;
+    const int shells[7] = {1, 2, 3, 4, 5, 6, 8};
+    for (int s = 0; s < 7; ++s)
+        for (int a = -2; a <= 2; ++a)
+            for (int b = -2; b <= 2; ++b)
+                for (int c = -2; c <= 2; ++c) {
+                    if (a * a + b * b + c * c != shells[s]) continue;
+                    const int last = c != 0 ? c : (b != 0 ? b : a);
+                    if (last < 0) continue;
+                    T.c[k][0] = a;
+                    T.c[k][1] = b;
+                    T.c[k][2] = c;
+                    T.p[k] = belt_weight_p(shells[s]);
+                    T.w[k] = shells[s] == 1 ? 1.0 / 18.0 : (shells[s] == 2 ? 1.0 / 36.0 : 0.0);
+                    ++k;
+                }
+    return T;
+}
+
+struct Belts {
+    static constexpr int n = 46;
+    static constexpr BeltTable tab = make_belt_table();
+};
+
 }  // namespace mclbm

@@ -43,7 +43,18 @@ mclbm_status fail(mclbm_status s, const char *fmt, ...)
 
 int lattice_Q(int lattice) { return lattice == MCLBM_D2Q9 ? 9 : 19; }
 int ncomp_of(int model) { return model == MCLBM_SC_MP ? 1 : 2; }
-int nfield_of(int model) { return model == MCLBM_CG ? 3 : (model == MCLBM_SC_MP ? 1 : 2); }
+bool multirange_of(const mclbm_params &p)
+{
+    return p.Ga_R != 0.0 || p.Ga_B != 0.0 || p.Gr_R != 0.0 || p.Gr_B != 0.0;
+}
+// stencil-field values per node: CG drho_R, drho_B, rho^N; SC_MP psi; SC_MC
+// drho_R, drho_B (+ psi_R, psi_B with the multirange forces)
+int nfield_of(const mclbm_params &p)
+{
+    if (p.model == MCLBM_CG) return 3;
+    if (p.model == MCLBM_SC_MP) return 1;
+    return multirange_of(p) ? 4 : 2;
+}
 size_t storage_size(int prec) { return prec == MCLBM_FP64 ? 8 : (prec == MCLBM_FP16 ? 2 : 4); }
 size_t field_size(int prec) { return prec == MCLBM_FP64 ? 8 : 4; }
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -58,7 +69,7 @@ Layout layout_of(const mclbm_params &p)
     Layout L;
     L.fbytes = align256((size_t)ncomp_of(p.model) * lattice_Q(p.lattice) * N * storage_size(p.precision));
     L.field_off = 2 * L.fbytes;
-    L.gfield_off = L.field_off + align256((size_t)nfield_of(p.model) * N * field_size(p.precision));
+    L.gfield_off = L.field_off + align256((size_t)nfield_of(p) * N * field_size(p.precision));
     const bool rep = p.model == MCLBM_CG && p.Pi != 0.0;
     L.total = L.gfield_off + (rep ? align256(3 * N * field_size(p.precision)) : 0);
     return L;
@@ -69,7 +80,9 @@ KParams make_kparams(const mclbm_params &p);
 bool fused_ok(const mclbm_params &p, const Ops *ops)
 {
     FusedShape sh;
-    return ops && ops->has_fused() && fused_shape(make_kparams(p), sh, p.precision == MCLBM_FP64);
+    // the multirange forces read two nodes out: the one-node halo ring of the
+    // fused kernel does not hold them
+    return ops && ops->has_fused() && !multirange_of(p) && fused_shape(make_kparams(p), sh, p.precision == MCLBM_FP64);
 }
 
 mclbm_status validate(const mclbm_params *p)
@@ -104,6 +117,15 @@ mclbm_status validate(const mclbm_params *p)
         if (p->model == MCLBM_SC_MP && !(p->psi_rho0 > 0.0)) return fail(MCLBM_EINVAL, "psi_rho0 must be > 0");
         if (p->model == MCLBM_SC_MC && (!(p->rho0_B > 0.0) || !(p->rho0_X > 0.0)))
             return fail(MCLBM_EINVAL, "SC_MC needs rho0_B > 0 and rho0_X > 0");
+    }
+    if (multirange_of(*p)) {
+        if (p->model != MCLBM_SC_MC)
+            return fail(MCLBM_EINVAL, "the multirange couplings belong to the two-component Shan-Chen model");
+        if (p->lattice != MCLBM_D3Q19)
+            return fail(MCLBM_EUNSUPPORTED, "the multirange neighbourhood is three-dimensional (D3Q19 only)");
+        if (!(p->psi_rho0 > 0.0)) return fail(MCLBM_EINVAL, "psi_rho0 must be > 0");
+        if (!std::isfinite(p->Ga_R) || !std::isfinite(p->Ga_B) || !std::isfinite(p->Gr_R) || !std::isfinite(p->Gr_B))
+            return fail(MCLBM_EINVAL, "multirange couplings must be finite");
     }
     if (p->kernel < 0 || p->kernel > 2) return fail(MCLBM_EINVAL, "bad kernel choice %d", p->kernel);
     const Ops *ops = get_ops(p->lattice, p->precision, p->model, p->model == MCLBM_CG && p->Pi != 0.0);
@@ -175,6 +197,11 @@ KParams make_kparams(const mclbm_params &p)
     K.Pi = p.Pi;
     K.chi = p.chi;
     K.sc_mid = 0.5 * (p.rho0_R + p.rho0_B);
+    K.multirange = multirange_of(p) ? 1 : 0;
+    K.Ga[0] = p.Ga_R;
+    K.Ga[1] = p.Ga_B;
+    K.Gr[0] = p.Gr_R;
+    K.Gr[1] = p.Gr_B;
     return K;
 }
 

@@ -47,6 +47,8 @@ struct KParams {
     double xpref;        // SC_MC: G_RB / rho0_X^2
     double Pi, chi;      // CG repulsion
     double sc_mid;       // SC_MP: (rho0_R + rho0_B)/2, the inside/outside threshold
+    int multirange;      // SC_MC: multirange forces on (psi_R, psi_B follow the densities in the field)
+    double Ga[2], Gr[2]; // SC_MC multirange attraction / repulsion couplings per species
 };
 
 // Arithmetic parameters of the collision in the kernel's own types (C for
@@ -62,6 +64,7 @@ struct HP {
     C halfA, g_min;
     C om[2];
     C G, psi_rho0, xpref, Pi, chi;
+    C Ga[2], Gr[2];
     int enhanced;
 };
 
@@ -73,6 +76,8 @@ __device__ __forceinline__ HP<C, M> make_hp(const KParams &P)
         H.rho0[k] = (M)P.rho0[k];
         H.inv_nu[k] = (M)P.inv_nu[k];
         H.om[k] = (C)P.om[k];
+        H.Ga[k] = (C)P.Ga[k];
+        H.Gr[k] = (C)P.Gr[k];
         for (int q = 0; q < 3; ++q) {
             H.phiM[k][q] = (M)P.phi[k][q];
             H.corrM[k][q] = (M)P.corr[k][q];
@@ -130,6 +135,16 @@ __device__ __forceinline__ long long stencil_node(const KParams &P, int x, int y
     const int qx = stencil_coord(x + L::cx[i], P.nx, P.bc[0]);
     const int qy = stencil_coord(y + L::cy[i], P.ny, P.bc[1]);
     const int qz = stencil_coord(z + L::cz[i], P.nz, P.bc[2]);
+    return (long long)qx + (long long)P.nx * ((long long)qy + (long long)P.ny * qz);
+}
+
+// Node read at x + (cx, cy, cz) for offsets up to two nodes (the multirange
+// neighbourhood): wrap periodic axes, clamp otherwise.
+__device__ __forceinline__ long long stencil_at(const KParams &P, int x, int y, int z, int cx, int cy, int cz)
+{
+    const int qx = stencil_coord(x + cx, P.nx, P.bc[0]);
+    const int qy = stencil_coord(y + cy, P.ny, P.bc[1]);
+    const int qz = stencil_coord(z + cz, P.nz, P.bc[2]);
     return (long long)qx + (long long)P.nx * ((long long)qy + (long long)P.ny * qz);
 }
 

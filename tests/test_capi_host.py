@@ -34,7 +34,7 @@ def test_library_exports_every_declared_function(M):
 
 
 def test_version_and_status_strings(M):
-    assert M.version() == (1, 2)
+    assert M.version() == (2, 0)
     L = M.lib()
     for s in (0, 1, -1, -2, -3, -4):
         assert L.mclbm_status_str(s)
@@ -43,7 +43,7 @@ def test_version_and_status_strings(M):
 
 def test_defaults(M):
     p = M.params_default(M.D3Q19, M.CG)
-    assert p["abi_version"] == 1 and p["beta"] == 0.7 and p["alpha_B"] == 0.2
+    assert p["abi_version"] == 2 and p["beta"] == 0.7 and p["alpha_B"] == 0.2
     assert (p["nx"], p["ny"], p["nz"]) == (64, 64, 64)
     assert M.params_default(M.D2Q9, M.CG)["nz"] == 1
 
@@ -146,3 +146,24 @@ def test_interface_observables_reject_bad_arguments_without_a_device(M):
     assert L.mclbm_interface_crossings(None, 0, 0, 0, pos, 4, ctypes.byref(n)) == -1
     assert L.mclbm_plane_area(None, 0, 0, ctypes.byref(a)) == -1
     assert L.mclbm_droplets(None, 4, ctypes.byref(n), sizes) == -1
+
+
+def test_multirange_argument_rules(M):
+    """Multirange couplings need the two-component Shan-Chen model (EINVAL),
+    D3Q19 (EUNSUPPORTED on D2Q9) and the two-pass kernels (EUNSUPPORTED when
+    the fused kernel is requested); with all four zero nothing changes."""
+    mr = dict(Ga_R=-9.0, Ga_B=-8.0, Gr_R=8.1, Gr_B=7.1, psi_rho0=0.83, rho0_X=0.83)
+    with pytest.raises(M.MclbmError) as e:
+        M.state_bytes(M.make_params(lattice=M.D3Q19, model=M.CG, **mr))
+    assert e.value.status == -1
+    with pytest.raises(M.MclbmError) as e:
+        M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, model=M.SC_MC, **mr))
+    assert e.value.status == -2
+    with pytest.raises(M.MclbmError) as e:
+        M.state_bytes(M.make_params(lattice=M.D3Q19, model=M.SC_MC, kernel=M.KERNEL_FUSED, **mr))
+    assert e.value.status == -2
+    p = M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=M.FP32, nx=32, ny=16, nz=8, **mr)
+    q = dict(p, Ga_R=0.0, Ga_B=0.0, Gr_R=0.0, Gr_B=0.0)
+    N = 32 * 16 * 8
+    # two more stencil fields (psi of each species) with the multirange forces
+    assert M.state_bytes(p) - M.state_bytes(q) == (4 - 2) * N * 4
