@@ -318,3 +318,31 @@ def test_ligament_contraction_enhanced_equilibrium(M):
         say(f"[ligament] enhanced={enh}: endpoint speed / analytic = {ratio[enh]:.3f}")
     assert abs(ratio[1] - 1.0) < 0.10
     assert ratio[0] < 0.85 * ratio[1]
+
+
+def test_rayleigh_plateau_criterion(M):
+    """A periodic jet R0 = 12 with a 0.1 R0 sinusoidal perturbation of
+    wavelength lambda (one wavelength per box, 64x64xlambda, CG, sigma via
+    A = 0.0675, tau = 1, FP32): the droplet counter sees it break into a main
+    drop and a satellite when 2 pi R0 < lambda (lambda = 96, 128; measured at
+    ~5500 and ~6250 steps) and stay one cylinder when 2 pi R0 > lambda
+    (lambda = 64); the satellite is smaller at the larger wavenumber
+    kappa = 2 pi R0 / lambda, as in the breakup section."""
+    R0 = 12.0
+    result = {}
+    for lam in (64, 96, 128):
+        shape = (lam, 64, 64)
+        rR, rB = inputs.jet(shape, R0, float(lam), 0.1, 0.0)
+        p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=64, ny=64, nz=lam, A=0.0675)
+        s = M.Sim(p)
+        s.init_equilibrium(rR, rB)
+        st, _ = s.step(10000, check_every=1000)
+        assert st == M.OK
+        result[lam] = s.droplets(8)
+        s.close()
+        say(f"[rayleigh-plateau] lambda={lam} kappa={2 * math.pi * R0 / lam:.3f}: {result[lam]}")
+    assert result[64][0] == 1
+    for lam in (96, 128):
+        n, sizes = result[lam]
+        assert n == 2 and sizes[1] < 0.05 * sizes[0]
+    assert result[96][1][1] < result[128][1][1]
