@@ -198,6 +198,9 @@ def main():
                     help="only run a plain device copy of one step's population bytes (counter calibration)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only time the step's memory patterns without stencil or collision (ceilings)")
+    ap.add_argument("--sweep", choices=["density", "viscosity"],
+                    help="only run a static-droplet Laplace study of the paper as one GPU batch")
+    ap.add_argument("--sweep-steps", type=int, default=100_000)
     ap.add_argument("--model", default="CG", choices=sorted(MODELS))
     ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
     args = ap.parse_args()
@@ -206,6 +209,12 @@ def main():
         return
     if args.stream_probe:
         stream_probe(args.size)
+        return
+    if args.sweep:
+        from paper_2110_05197_amd import sweeps
+        out = sweeps.run(args.sweep, steps=args.sweep_steps,
+                         log=lambda *a: print(*a, file=sys.stderr, flush=True))
+        print(json.dumps(out))
         return
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the "

@@ -66,3 +66,25 @@ def test_served_result_equals_solo(M):
         b1.close()
         assert st1[0] == stt
         assert np.array_equal(s.export_f().cpu().numpy(), fm)
+
+
+def test_laplace_sweep_machinery(M):
+    """The static-droplet sweep (sweeps.run) on a reduced case: R = 8, 12,
+    density ratios 1 and 1000 in one batch (FP32 and mixed groups), 20000
+    steps: no divergence, sigma_cal within 40 % of sigma_th, the measured
+    radius within 1 of the initial one, and the Laplace error smaller at
+    the larger radius for density ratio 1."""
+    from paper_2110_05197_amd import sweeps
+    orig = sweeps.cases
+    try:
+        sweeps.cases = lambda study, radii=(8, 12): [(R, g, 1.0) for g in (1, 1000) for R in radii]
+        out = sweeps.run("density", steps=20000, radii=(8, 12), chunk=500, log=lambda *a: None)
+    finally:
+        sweeps.cases = orig
+    res = out["results"]
+    assert len(res) == 4 and not any(m["diverged"] for m in res)
+    for m in res:
+        assert abs(m["sigma_cal"] - 0.01) < 0.004
+        assert abs(m["R"] - m["R0"]) < 1.0
+    e1 = {m["R0"]: m["E"] for m in res if m["gamma"] == 1}
+    assert e1[12] < e1[8]
