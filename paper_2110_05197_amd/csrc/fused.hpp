@@ -1,12 +1,13 @@
 // fused.hpp -- one-pass D3Q19 step: each block owns a TX x TY column of
 // nodes and marches it through a chunk of TZ planes.  The stencil inputs
-// (colour-gradient densities / pseudopotential) of plane z+1 are computed
-// from the populations as they are loaded, for the tile and a one-node x-y
-// halo ring, into a three-plane LDS ring; the tile's own populations stay in
-// registers from the load of plane z+1 to the collision of that plane one
-// iteration later.  Only the halo ring's populations are read twice (by this
-// block and its neighbour), so HBM traffic stays near one read and one write
-// of every population per step; no density field is written.
+// (colour-gradient densities / pseudopotential) of a plane are computed from
+// its populations as they are loaded (two planes ahead of the collision),
+// for the tile and a one-node x-y halo ring, into a four-plane LDS ring; a
+// tile node's populations wait one iteration in the thread's LDS slot and are
+// collided from registers.  Only the halo ring's populations are read twice
+// (by this block and its neighbour, mostly from L2), so HBM traffic stays
+// near one read and one write of every population per step; no density field
+// is written.
 //
 // Requires nx % TX == 0 and ny % TY == 0 (the host falls back to the
 // two-pass kernels otherwise); any nz.
