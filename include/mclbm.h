@@ -283,10 +283,20 @@ mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
  * boundaries in device descriptors.  target_steps[s] (host, n values) is the
  * number of further steps sim s should take; a sim stops when it reaches
  * its target or diverges.  Sims must not be stepped on their own while in a
- * batch.  The per-node arithmetic is the same as mclbm_step's two-pass
- * kernel, so a sim's result is bitwise the same alone and in any batch. */
+ * batch.  D3Q19 sims that have a one-pass kernel (no repulsion force, no
+ * multirange forces) with nx % 64 == 0 and ny % 4 == 0, and whose kernel is
+ * not MCLBM_KERNEL_TWO_PASS, step in one batched one-pass launch per group
+ * (64 x 4 columns, z-chunks sized so that the group fills the chip); the
+ * others in batched two-pass launches.  The per-node arithmetic is the same
+ * as mclbm_step's, so a sim's result is bitwise the same alone (either
+ * kernel) and in any batch. */
 mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t *target_steps,
                                 void *stream, mclbm_batch **out);
+
+/* The kernel each sim runs in the batch: MCLBM_KERNEL_FUSED or
+ * MCLBM_KERNEL_TWO_PASS (host array of n, in the order given to
+ * mclbm_batch_create).  Host only; EINVAL on NULL. */
+mclbm_status mclbm_batch_kernels(const mclbm_batch *b, int32_t *kernels);
 
 /* Enqueue ksteps batch steps.  use_graph != 0 captures the ksteps launches
  * in a HIP graph once (per ksteps value) and replays it. */

@@ -114,6 +114,7 @@ def lib():
                                    _vp, ctypes.POINTER(_vp)],
             "mclbm_batch_step": [_vp, ctypes.c_int32, ctypes.c_int32],
             "mclbm_batch_status": [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)],
+            "mclbm_batch_kernels": [_vp, ctypes.POINTER(ctypes.c_int32)],
             "mclbm_batch_destroy": [_vp],
         }
         for name, args in sigs.items():
@@ -371,6 +372,12 @@ class Batch:
         steps = (ctypes.c_int64 * n)()
         _check(lib().mclbm_batch_status(self._h, st, steps), "mclbm_batch_status")
         return list(st), list(steps)
+
+    def kernels(self):
+        """KERNEL_FUSED or KERNEL_TWO_PASS per sim: the batched kernel it runs."""
+        k = (ctypes.c_int32 * len(self.sims))()
+        _check(lib().mclbm_batch_kernels(self._h, k), "mclbm_batch_kernels")
+        return list(k)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 
 namespace mclbm {
 
@@ -58,10 +59,11 @@ constexpr int fused_lds_bytes()
            + NComp<MODEL>::n * D3Q19::Q * TX * TY * (int)sizeof(typename Prec<PR>::C);
 }
 
+// One block's work: the TX x TY column at (x0, y0), planes [z0, z1).
 template <int PR, int MODEL, int TX, int TY, bool PERIODIC>
-__global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec<PR>::S *__restrict__ src,
-                                                  typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int TZ,
-                                                  int tiles_x, int tiles_y)
+__device__ __forceinline__ void fused_column(const KParams &P, const typename Prec<PR>::S *__restrict__ src,
+                                             typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int x0, int y0,
+                                             int z0, int z1, unsigned char *smem)
 {
     using L = D3Q19;
     using C = typename Prec<PR>::C;
@@ -76,17 +78,12 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
     // are read while plane z+2 is written), then each thread's private slot
     // holding the populations of plane z+1 (laid out [population][thread] so
     // that a wavefront's accesses are contiguous).
-    extern __shared__ __align__(16) unsigned char smem[];
     FT (*lds)[NF][PL] = reinterpret_cast<FT (*)[NF][PL]>(smem);
     C *pop = reinterpret_cast<C *>(smem + fused_ring_bytes<MODEL, TX, TY, FT>());
 
     const long long N = P.N;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const HP<C, M> H = make_hp<C, M>(P);
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-    const int z1 = min(z0 + TZ, nz);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
@@ -246,6 +243,105 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
     }
     const unsigned long long any = __ballot(bad);
     if (any != 0ull && (tid & 63) == 0) atomicOr(flag, 1u);
+}
+
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC>
+__global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec<PR>::S *__restrict__ src,
+                                                  typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int TZ,
+                                                  int tiles_x, int tiles_y)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
+    const int z0 = bz * TZ;
+    fused_column<PR, MODEL, TX, TY, PERIODIC>(P, src, dst, flag, bx * TX, by * TY, z0, min(z0 + TZ, P.nz), smem);
+}
+
+// Batched one-pass step: the blocks of all eligible simulations of a group
+// (D3Q19, nx a multiple of kBatchTX, ny of kBatchTY) in one launch; a block
+// finds its simulation in the descriptor array (one-pass block ranges),
+// skips it unless it is running, and processes one column of that
+// simulation, with the periodic push when all its boundaries are periodic
+// and the boundary-aware push otherwise.  The per-node arithmetic is the solo
+// kernels', so a batched simulation evolves bitwise as it would alone.
+// 64-wide rows: at 16 or 32 nodes the rows of the x-shifted pushes split
+// cache lines between neighbouring blocks and the step runs at half speed.
+#ifndef MCLBM_BATCH_TX
+#define MCLBM_BATCH_TX 64
+#endif
+#ifndef MCLBM_BATCH_TY
+#define MCLBM_BATCH_TY 4
+#endif
+constexpr int kBatchTX = MCLBM_BATCH_TX, kBatchTY = MCLBM_BATCH_TY;
+
+__device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (D[mid].fblock0 <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int PR, int MODEL>
+__global__ __launch_bounds__(kBatchTX *kBatchTY) void kb_fused(SimDesc *D, int nsims)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int s = find_sim_fused(D, nsims, blockIdx.x);
+    const SimDesc &d = D[s];
+    if (d.state != 0) return;
+    const long long b = blockIdx.x - d.fblock0;
+    const int tiles_x = d.P.nx / kBatchTX, tiles_y = d.P.ny / kBatchTY;
+    const int bx = (int)(b % tiles_x), by = (int)((b / tiles_x) % tiles_y), bz = (int)(b / ((long long)tiles_x * tiles_y));
+    const int x0 = bx * kBatchTX, y0 = by * kBatchTY, z0 = bz * d.ftz, z1 = min(z0 + d.ftz, d.P.nz);
+    using S = typename Prec<PR>::S;
+    const S *src = global_ptr<const S>(d.f[d.cur]);
+    S *dst = global_ptr<S>(d.f[d.cur ^ 1]);
+    unsigned *flag = global_ptr<unsigned>(d.flag);
+    if (d.P.bc[0] == 0 && d.P.bc[1] == 0 && d.P.bc[2] == 0)
+        fused_column<PR, MODEL, kBatchTX, kBatchTY, true>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
+    else
+        fused_column<PR, MODEL, kBatchTX, kBatchTY, false>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
+}
+
+// Planes per column of a batched simulation.  A column advances one plane at
+// a time, each plane a chain of dependent loads, arithmetic and a barrier, so
+// a launch with few columns in flight is bound by that chain's latency: the
+// z-chunk is chosen so that the group's columns fill the chip
+// (kBatchTargetBlocks blocks), within [kBatchMinTz, 48] planes (three extra
+// planes of stencil loads per chunk), and balanced over nz.
+#ifndef MCLBM_BATCH_TARGET_BLOCKS
+#define MCLBM_BATCH_TARGET_BLOCKS 1024
+#endif
+#ifndef MCLBM_BATCH_MIN_TZ
+#define MCLBM_BATCH_MIN_TZ 4
+#endif
+constexpr long long kBatchTargetBlocks = MCLBM_BATCH_TARGET_BLOCKS;
+constexpr int kBatchMinTz = MCLBM_BATCH_MIN_TZ;
+
+// plane_columns: sum over the group's one-pass sims of (nx / TX)(ny / TY) nz
+inline int batch_group_tz(long long plane_columns)
+{
+    const long long t = (plane_columns + kBatchTargetBlocks - 1) / kBatchTargetBlocks;
+    return (int)std::min<long long>(48, std::max<long long>(kBatchMinTz, t));
+}
+inline int batch_fused_tz(int nz, int group_tz)
+{
+    const int chunks = (nz + group_tz - 1) / group_tz;
+    return (nz + chunks - 1) / chunks;
+}
+
+template <int PR, int MODEL>
+void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s)
+{
+    constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, kBatchTY>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((kb_fused<PR, MODEL>), dim3((unsigned)fblocks), dim3(kBatchTX * kBatchTY), lds, s, D, n);
 }
 
 struct FusedShape {

@@ -2,6 +2,8 @@
 // bodies, and the per-instantiation launcher table used by the C ABI.
 #pragma once
 
+#include <cstdint>
+
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -131,9 +133,21 @@ struct SimDesc {
     long long block0, nblocks;     // node-parallel grid slice
     long long oblock0, onblocks;   // outflow-face grid slice
     long long ocount;              // outflow face nodes
+    long long fblock0, fnblocks;   // one-pass (fused) grid slice; 0 blocks: two-pass
+    int ftz;                        // planes per fused column
     long long steps, target;
     int cur, state;
 };
+
+// A pointer read from memory is generic (flat) to the compiler; flat loads
+// count against the LDS wait counter as well as the vector-memory one, so an
+// LDS wait would also wait for every load in flight.  The descriptors' state
+// pointers are device memory: convert them to global-address-space pointers.
+template <class T>
+__device__ __forceinline__ T *global_ptr(const void *p)
+{
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
 
 __device__ __forceinline__ int find_sim(const SimDesc *D, int n, long long b, bool outflow)
 {
@@ -155,9 +169,9 @@ __global__ __launch_bounds__(kBlock) void kb_density(SimDesc *D, int nsims)
     const long long n = (blockIdx.x - d.block0) * kBlock + threadIdx.x;
     bool bad = false;
     if (n < d.P.N)
-        bad = density_body<L, PR, MODEL>(d.P, (const typename Prec<PR>::S *)d.f[d.cur],
-                                         (typename Prec<PR>::F *)d.field, n);
-    flag_if_bad(d.flag, bad);
+        bad = density_body<L, PR, MODEL>(d.P, global_ptr<const typename Prec<PR>::S>(d.f[d.cur]),
+                                         global_ptr<typename Prec<PR>::F>(d.field), n);
+    flag_if_bad(global_ptr<unsigned>(d.flag), bad);
 }
 
 template <class L, int PR, int MODEL, bool REP>
@@ -168,10 +182,10 @@ __global__ __launch_bounds__(kBlock) void kb_collide(SimDesc *D, int nsims)
     if (d.state != 0) return;
     const long long n = (blockIdx.x - d.block0) * kBlock + threadIdx.x;
     if (n < d.P.N)
-        collide_body<L, PR, MODEL, REP>(d.P, (const typename Prec<PR>::S *)d.f[d.cur],
-                                        (typename Prec<PR>::S *)d.f[d.cur ^ 1],
-                                        (const typename Prec<PR>::F *)d.field,
-                                        (const typename Prec<PR>::F *)d.gfield, n);
+        collide_body<L, PR, MODEL, REP>(d.P, global_ptr<const typename Prec<PR>::S>(d.f[d.cur]),
+                                        global_ptr<typename Prec<PR>::S>(d.f[d.cur ^ 1]),
+                                        global_ptr<const typename Prec<PR>::F>(d.field),
+                                        global_ptr<const typename Prec<PR>::F>(d.gfield), n);
 }
 
 template <class L, int PR>
@@ -182,7 +196,8 @@ __global__ __launch_bounds__(kBlock) void kb_gradN(SimDesc *D, int nsims)
     if (d.state != 0) return;
     const long long n = (blockIdx.x - d.block0) * kBlock + threadIdx.x;
     if (n < d.P.N)
-        gradN_body<L, PR>(d.P, (const typename Prec<PR>::F *)d.field, (typename Prec<PR>::F *)d.gfield, n);
+        gradN_body<L, PR>(d.P, global_ptr<const typename Prec<PR>::F>(d.field),
+                          global_ptr<typename Prec<PR>::F>(d.gfield), n);
 }
 
 template <class L, int PR, int MODEL>
@@ -194,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void kb_outflow(SimDesc *D, int nsims)
     const long long idx = (blockIdx.x - d.oblock0) * kBlock + threadIdx.x;
     int x, y, z;
     if (idx < d.ocount && outflow_face_node(d.P, idx, x, y, z))
-        outflow_body<L, NComp<MODEL>::n>(d.P, (typename Prec<PR>::S *)d.f[d.cur ^ 1], x, y, z);
+        outflow_body<L, NComp<MODEL>::n>(d.P, global_ptr<typename Prec<PR>::S>(d.f[d.cur ^ 1]), x, y, z);
 }
 
 }  // namespace mclbm

@@ -85,6 +85,14 @@ bool fused_ok(const mclbm_params &p, const Ops *ops)
     return ops && ops->has_fused() && !multirange_of(p) && fused_shape(make_kparams(p), sh, p.precision == MCLBM_FP64);
 }
 
+// The batched one-pass kernel takes kBatchTX x kBatchTY columns; a sim whose
+// kernel is pinned to the two-pass path keeps it.
+bool batch_fused_ok(const mclbm_params &p, const Ops *ops)
+{
+    return ops && ops->has_fused() && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS
+           && p.nx % kBatchTX == 0 && p.ny % kBatchTY == 0;
+}
+
 mclbm_status validate(const mclbm_params *p)
 {
     if (!p) return fail(MCLBM_EINVAL, "params is NULL");
@@ -435,7 +443,7 @@ struct mclbm_batch {
     struct Group {
         const Ops *ops;
         int first, count;
-        long long blocks, oblocks;
+        long long blocks, fblocks, oblocks;
         bool any_outflow;
     };
     std::vector<Group> groups;
@@ -832,8 +840,16 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         g.first = slot;
         g.count = (int)groups[key].size();
         g.blocks = 0;
+        g.fblocks = 0;
         g.oblocks = 0;
         g.any_outflow = false;
+        long long plane_columns = 0;
+        for (int idx : groups[key]) {
+            const mclbm_params &q = sims[idx]->prm;
+            if (batch_fused_ok(q, sims[idx]->ops))
+                plane_columns += (long long)(q.nx / kBatchTX) * (q.ny / kBatchTY) * q.nz;
+        }
+        const int group_tz = batch_group_tz(plane_columns);
         for (int idx : groups[key]) {
             mclbm_sim *s = sims[idx];
             (void)hipStreamSynchronize(s->stream);
@@ -846,8 +862,16 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
             d.gfield = s->gfield;
             d.flag = s->d_flag;
             d.block0 = g.blocks;
-            d.nblocks = grid_of(s->kp.N);
-            g.blocks += d.nblocks;
+            d.fblock0 = g.fblocks;
+            if (batch_fused_ok(s->prm, s->ops)) {
+                d.ftz = batch_fused_tz(s->prm.nz, group_tz);
+                d.fnblocks = (long long)(s->prm.nx / kBatchTX) * (s->prm.ny / kBatchTY)
+                             * ((s->prm.nz + d.ftz - 1) / d.ftz);
+                g.fblocks += d.fnblocks;
+            } else {
+                d.nblocks = grid_of(s->kp.N);
+                g.blocks += d.nblocks;
+            }
             d.ocount = s->kp.has_outflow ? outflow_count(s->kp) : 0;
             d.oblock0 = g.oblocks;
             d.onblocks = grid_of(d.ocount);
@@ -883,7 +907,8 @@ static void batch_enqueue(mclbm_batch *b, int k)
     const int n = (int)b->sims.size();
     for (int t = 0; t < k; ++t) {
         for (const auto &g : b->groups)
-            g.ops->batch_step(b->d_desc + g.first, g.count, g.blocks, g.oblocks, g.any_outflow, b->stream);
+            g.ops->batch_step(b->d_desc + g.first, g.count, g.blocks, g.fblocks, g.oblocks, g.any_outflow,
+                              b->stream);
         hipLaunchKernelGGL(kb_advance, dim3((n + 63) / 64), dim3(64), 0, b->stream, b->d_desc, n);
     }
 }
@@ -908,6 +933,14 @@ mclbm_status mclbm_batch_step(mclbm_batch *b, int32_t ksteps, int32_t use_graph)
         b->graph_k = ksteps;
     }
     MCLBM_HIP(hipGraphLaunch(b->exec, b->stream));
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_batch_kernels(const mclbm_batch *b, int32_t *kernels)
+{
+    if (!b || !kernels) return fail(MCLBM_EINVAL, "bad batch kernels arguments");
+    for (size_t slot = 0; slot < b->order.size(); ++slot)
+        kernels[b->order[slot]] = b->h_desc[slot].fnblocks > 0 ? MCLBM_KERNEL_FUSED : MCLBM_KERNEL_TWO_PASS;
     return MCLBM_OK;
 }
 

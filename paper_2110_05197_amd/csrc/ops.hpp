@@ -25,9 +25,10 @@ struct Ops {
                          double *u, hipStream_t s) const = 0;
     virtual void obs(const KParams &P, const void *f, const void *field, const EpsTable &e, double *partials,
                      int nblocks, hipStream_t s) const = 0;
-    // batched step pieces over a group of descriptors
-    virtual void batch_step(SimDesc *D, int n, long long blocks, long long oblocks, bool any_outflow,
-                            hipStream_t s) const = 0;
+    // batched step over a group of descriptors: `blocks` two-pass blocks,
+    // `fblocks` one-pass blocks, `oblocks` outflow blocks
+    virtual void batch_step(SimDesc *D, int n, long long blocks, long long fblocks, long long oblocks,
+                            bool any_outflow, hipStream_t s) const = 0;
     // interface observables: phase indicator of a node set, per-block red
     // fraction partial sums over a node set, initial component labels
     virtual void phase_sample(const KParams &P, const void *f, const NodeSet &ns, double *out,
@@ -55,6 +56,8 @@ template <class L, int PR, int MODEL, bool REP> constexpr bool fused_available()
 }
 template <int PR, int MODEL>
 void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);
+template <int PR, int MODEL>
+void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s);
 
 template <class L, int PR, int MODEL, bool REP>
 struct OpsT final : Ops {
@@ -134,12 +137,18 @@ struct OpsT final : Ops {
         hipLaunchKernelGGL((k_phase_labels<L, PR, MODEL>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
                            (const S *)f, labels);
     }
-    void batch_step(SimDesc *D, int n, long long blocks, long long oblocks, bool any_outflow,
+    void batch_step(SimDesc *D, int n, long long blocks, long long fblocks, long long oblocks, bool any_outflow,
                     hipStream_t s) const override
     {
-        hipLaunchKernelGGL((kb_density<L, PR, MODEL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
-        if constexpr (REP) hipLaunchKernelGGL((kb_gradN<L, PR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
-        hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
+        if (blocks > 0) {
+            hipLaunchKernelGGL((kb_density<L, PR, MODEL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
+            if constexpr (REP)
+                hipLaunchKernelGGL((kb_gradN<L, PR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
+            hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
+        }
+        if constexpr (fused_available<L, PR, MODEL, REP>()) {
+            if (fblocks > 0) launch_batch_fused<PR, MODEL>(D, n, fblocks, s);
+        }
         if (any_outflow && oblocks > 0)
             hipLaunchKernelGGL((kb_outflow<L, PR, MODEL>), dim3((unsigned)oblocks), dim3(kBlock), 0, s, D, n);
     }

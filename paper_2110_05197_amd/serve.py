@@ -152,8 +152,7 @@ def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 5
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
         prec = int(rng.choice(precisions))
         lattice = M.D3Q19 if d3 else M.D2Q9
-        base = dict(lattice=lattice, nx=L, ny=L, nz=L if d3 else 1, precision=prec,
-                    kernel=M.KERNEL_TWO_PASS)
+        base = dict(lattice=lattice, nx=L, ny=L, nz=L if d3 else 1, precision=prec)
         # heavy fluid more viscous: nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)
         nu0 = 1.0 / 6.0
         nuR, nuB = nu0 * math.sqrt(nu_ratio), nu0 / math.sqrt(nu_ratio)

@@ -54,8 +54,7 @@ def case_params(M, R, gamma, nu_ratio):
     nuR, nuB = nu0 * math.sqrt(nu_ratio), nu0 / math.sqrt(nu_ratio)
     prec = M.MIXED if gamma >= 100 else M.FP32
     p = M.make_params(lattice=M.D3Q19, precision=prec, nx=L, ny=L, nz=L, rho0_R=float(gamma),
-                      rho0_B=1.0, tau_R=0.5 + 3 * nuR, tau_B=0.5 + 3 * nuB,
-                      kernel=M.KERNEL_TWO_PASS)
+                      rho0_B=1.0, tau_R=0.5 + 3 * nuR, tau_B=0.5 + 3 * nuB)
     return M.params_from_sigma(p, SIGMA)
 
 

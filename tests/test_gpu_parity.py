@@ -371,6 +371,59 @@ def test_batch_invariance_bitwise(M):
             assert np.array_equal(s.export_f().cpu().numpy(), f)
 
 
+def test_batch_one_pass_bitwise(M):
+    """Batched one-pass columns (64 x 4) beside batched two-pass sims in the
+    same batch: every sim ends bitwise equal to its solo two-pass run; every
+    precision, all three models, walls and outflow, z-chunks with a one-plane
+    last chunk (nz = 101 -> 25 x 4 + 1)."""
+    def sc_mp(shape):
+        a, b = inputs.droplet(shape, 3.0, 1.9, 0.12)
+        return a + b, None, None
+
+    D3, F, T = M.D3Q19, M.KERNEL_FUSED, M.KERNEL_TWO_PASS
+    cases = [  # params, fields, steps, expected batched kernel
+        (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=16, nz=20, A=0.02), None, 23, F),
+        (M.make_params(lattice=D3, precision=M.FP64, nx=64, ny=8, nz=101, A=0.02, bc=(1, 0, 2)), None, 17, F),
+        (M.make_params(lattice=D3, precision=M.FP16, nx=64, ny=8, nz=16, A=0.02, bc=(0, 1, 0)), None, 21, F),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=64, ny=12, nz=16, A=0.02, rho0_B=0.01), None, 19, F),
+        (M.make_params(lattice=D3, model=M.SC_MP, precision=M.FP32, nx=64, ny=8, nz=24, G=-5.0, rho0_R=1.9,
+                       rho0_B=0.12), "scmp", 25, F),
+        (M.make_params(lattice=D3, model=M.SC_MC, precision=M.FP32, nx=64, ny=8, nz=16, G_RB=1.2,
+                       bc=(2, 0, 1)), None, 27, F),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=32, ny=16, nz=16, A=0.01), None, 29, T),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=6, nz=16, A=0.01), None, 13, T),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=8, nz=16, A=0.02, Pi=0.01), None, 15, T),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=8, nz=16, A=0.02, kernel=T), None, 18, T),
+        (M.make_params(lattice=M.D2Q9, precision=M.FP32, nx=64, ny=32, nz=1, A=0.02), None, 31, T),
+    ]
+    inits = []
+    for i, (p, kind, _, _) in enumerate(cases):
+        shape = (p["nz"], p["ny"], p["nx"])
+        if kind == "scmp":
+            inits.append(sc_mp(shape))
+        else:
+            inits.append(cg_droplet_case(shape, 50 + i, gamma=p["rho0_R"] / p["rho0_B"], lattice=p["lattice"]))
+    solo = [gpu_run(M, p, *ini, n, kernel=1)[1] for (p, _, n, _), ini in zip(cases, inits)]
+    for use_graph in (False, True):
+        say(f"[batch one-pass] use_graph={use_graph}")
+        sims = []
+        for (p, _, _, _), (rR, rB, u) in zip(cases, inits):
+            s = M.Sim(p)
+            s.init_equilibrium(rR, rB, u)
+            sims.append(s)
+        b = M.Batch(sims, [n for (_, _, n, _) in cases])
+        assert b.kernels() == [k for (_, _, _, k) in cases]
+        for _ in range(5):
+            b.step(7, use_graph=use_graph)
+        st, steps = b.status()
+        b.close()
+        assert st == [M.DONE] * len(cases)
+        assert steps == [n for (_, _, n, _) in cases]
+        for i, (s, f) in enumerate(zip(sims, solo)):
+            assert np.array_equal(s.export_f().cpu().numpy(), f), f"case {i}"
+            s.close()
+
+
 def test_batch_stops_diverged_member(M):
     p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=16, ny=16, nz=16, A=0.02)
     shape = (16, 16, 16)
