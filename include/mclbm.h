@@ -265,7 +265,7 @@ mclbm_status mclbm_plane_area(mclbm_sim *sim, int32_t axis, int32_t pos, double 
 mclbm_status mclbm_droplets(mclbm_sim *sim, int32_t max, int32_t *count, int64_t *h_sizes);
 
 /* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass:
- * D3Q19 without the repulsion force, nx % 32 == 0 and ny % 4 == 0) or
+ * D3Q19 without the repulsion or multirange forces, ny % 4 == 0, any nx) or
  * MCLBM_KERNEL_TWO_PASS.  Host only; EINVAL on NULL. */
 mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
 
@@ -284,9 +284,11 @@ mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
  * number of further steps sim s should take; a sim stops when it reaches
  * its target or diverges.  Sims must not be stepped on their own while in a
  * batch.  D3Q19 sims that have a one-pass kernel (no repulsion force, no
- * multirange forces) with nx % 64 == 0 and ny % 4 == 0, and whose kernel is
- * not MCLBM_KERNEL_TWO_PASS, step in one batched one-pass launch per group
- * (64 x 4 columns, z-chunks sized so that the group fills the chip); the
+ * multirange forces), not in mixed precision, with nx % 64 == 0 and
+ * ny % 8 == 0 (ny % 4 == 0 in FP64), and whose kernel is not
+ * MCLBM_KERNEL_TWO_PASS, step in one batched
+ * one-pass launch per group (64 x 8 columns, 64 x 4 in FP64, z-chunks sized
+ * for the group); the
  * others in batched two-pass launches.  The per-node arithmetic is the same
  * as mclbm_step's, so a sim's result is bitwise the same alone (either
  * kernel) and in any batch. */

@@ -59,8 +59,11 @@ constexpr int fused_lds_bytes()
            + NComp<MODEL>::n * D3Q19::Q * TX * TY * (int)sizeof(typename Prec<PR>::C);
 }
 
-// One block's work: the TX x TY column at (x0, y0), planes [z0, z1).
-template <int PR, int MODEL, int TX, int TY, bool PERIODIC>
+// One block's work: the TX x TY column at (x0, y0), planes [z0, z1).  An
+// EDGE column is the last one in x when TX does not divide nx: its first
+// w = nx - x0 threads hold nodes, the others only take part in the barriers,
+// and its +x halo is the column at x0 + w.
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool EDGE = false>
 __device__ __forceinline__ void fused_column(const KParams &P, const typename Prec<PR>::S *__restrict__ src,
                                              typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int x0, int y0,
                                              int z0, int z1, unsigned char *smem)
@@ -88,15 +91,17 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
     const int my_slot = (ly + 1) * HX + (lx + 1);
+    const int w = EDGE ? min(TX, nx - x0) : TX;   // nodes per row of this column
+    const bool act = !EDGE || lx < w;
 
     // halo ring node of this thread: rows y0-1 and y0+TY, then columns
-    // x0-1 and x0+TX
-    const bool has_h = tid < NH;
+    // x0-1 and x0+w
     int hx = 0, hy = 0;
     if (tid < HX) { hx = tid - 1; hy = -1; }
     else if (tid < 2 * HX) { hx = tid - HX - 1; hy = TY; }
     else if (tid < 2 * HX + TY) { hx = -1; hy = tid - 2 * HX; }
-    else { hx = TX; hy = tid - 2 * HX - TY; }
+    else { hx = w; hy = tid - 2 * HX - TY; }
+    const bool has_h = tid < NH && hx <= w;
     const int h_slot = (hy + 1) * HX + (hx + 1);
     const int hgx = stencil_coord(x0 + hx, nx, P.bc[0]);
     const int hgy = stencil_coord(y0 + hy, ny, P.bc[1]);
@@ -126,16 +131,18 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
         // prologue: stencil values of planes z0-1, z0, z0+1; populations of z0, z0+1
         C tmp[K][Q];
         M d2[2], j2[3];
-        load_node<L, K>(src, N, n_xy + zoff(z0 - 1), tmp);
-        put(z0 - 1, my_slot, tmp, d2, j2, true);
-        load_node<L, K>(src, N, n_xy + zoff(z0), c);
-        put(z0, my_slot, c, drc, jc, true);
-        load_node<L, K>(src, N, n_xy + zoff(z0 + 1), tmp);
-        put(z0 + 1, my_slot, tmp, drn, jn, true);
+        if (act) {
+            load_node<L, K>(src, N, n_xy + zoff(z0 - 1), tmp);
+            put(z0 - 1, my_slot, tmp, d2, j2, true);
+            load_node<L, K>(src, N, n_xy + zoff(z0), c);
+            put(z0, my_slot, c, drc, jc, true);
+            load_node<L, K>(src, N, n_xy + zoff(z0 + 1), tmp);
+            put(z0 + 1, my_slot, tmp, drn, jn, true);
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int i = 0; i < Q; ++i) pop[(k * Q + i) * NT + tid] = tmp[k][i];
+                for (int i = 0; i < Q; ++i) pop[(k * Q + i) * NT + tid] = tmp[k][i];
+        }
         if (has_h)
             for (int p = z0 - 1; p <= z0 + 1; ++p) {
                 load_node<L, K>(src, N, h_xy + zoff(p), tmp);
@@ -149,12 +156,12 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
         const bool ahead = z + 2 <= z1;
         RawNode<L, K, typename Prec<PR>::S, C> dr_, hr_;
         if (ahead) {
-            dr_.load(src, N, n_xy + zoff(z + 2));
+            if (act) dr_.load(src, N, n_xy + zoff(z + 2));
             if (has_h) hr_.load(src, N, h_xy + zoff(z + 2));
         }
 
         // 2. collide plane z with the stencil values of planes z-1, z, z+1
-        {
+        if (act) {
             C v[NF][Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
@@ -218,7 +225,7 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
         C d[K][Q];
         dr_.get(d);
         if (ahead) {
-            put(z + 2, my_slot, d, drd, jd, true);
+            if (act) put(z + 2, my_slot, d, drd, jd, true);
             if (has_h) {
                 C hh[K][Q];
                 hr_.get(hh);
@@ -245,7 +252,8 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
     if (any != 0ull && (tid & 63) == 0) atomicOr(flag, 1u);
 }
 
-template <int PR, int MODEL, int TX, int TY, bool PERIODIC>
+// RAGGED: TX does not divide nx, and the last column in x is an edge column.
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool RAGGED>
 __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec<PR>::S *__restrict__ src,
                                                   typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int TZ,
                                                   int tiles_x, int tiles_y)
@@ -253,26 +261,32 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
-    const int z0 = bz * TZ;
-    fused_column<PR, MODEL, TX, TY, PERIODIC>(P, src, dst, flag, bx * TX, by * TY, z0, min(z0 + TZ, P.nz), smem);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ, z1 = min(z0 + TZ, P.nz);
+    if constexpr (RAGGED) {
+        if (bx == tiles_x - 1) {
+            fused_column<PR, MODEL, TX, TY, PERIODIC, true>(P, src, dst, flag, x0, y0, z0, z1, smem);
+            return;
+        }
+    }
+    fused_column<PR, MODEL, TX, TY, PERIODIC>(P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
 // Batched one-pass step: the blocks of all eligible simulations of a group
-// (D3Q19, nx a multiple of kBatchTX, ny of kBatchTY) in one launch; a block
-// finds its simulation in the descriptor array (one-pass block ranges),
-// skips it unless it is running, and processes one column of that
+// (D3Q19, nx a multiple of 64, ny of the column height) in one launch; a
+// block finds its simulation in the descriptor array (one-pass block
+// ranges), skips it unless it is running, and processes one column of that
 // simulation, with the periodic push when all its boundaries are periodic
-// and the boundary-aware push otherwise.  The per-node arithmetic is the solo
-// kernels', so a batched simulation evolves bitwise as it would alone.
-// 64-wide rows: at 16 or 32 nodes the rows of the x-shifted pushes split
-// cache lines between neighbouring blocks and the step runs at half speed.
-#ifndef MCLBM_BATCH_TX
-#define MCLBM_BATCH_TX 64
-#endif
-#ifndef MCLBM_BATCH_TY
-#define MCLBM_BATCH_TY 4
-#endif
-constexpr int kBatchTX = MCLBM_BATCH_TX, kBatchTY = MCLBM_BATCH_TY;
+// and the boundary-aware push otherwise.  The per-node arithmetic is the
+// solo kernels', so a batched simulation evolves bitwise as it would alone.
+// Columns as in the solo kernel: 64-wide rows (at 16 or 32 nodes the rows of
+// the x-shifted pushes split cache lines between neighbouring blocks and the
+// step runs at half speed), 8 rows (4 in FP64), one block per compute unit.
+// No masked edge columns here (the batched two-pass kernels were as fast on
+// the ragged sizes measured, 96^3 and 160^3), and no mixed-precision variant:
+// with its two inlined column variants (periodic and boundary-aware push) it
+// spills registers and runs behind the batched two-pass kernels.
+constexpr int kBatchTX = 64;
+constexpr int batch_ty(int precision) { return precision == 0 ? 4 : 8; }
 
 __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long b)
 {
@@ -285,8 +299,9 @@ __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long
 }
 
 template <int PR, int MODEL>
-__global__ __launch_bounds__(kBatchTX *kBatchTY) void kb_fused(SimDesc *D, int nsims)
+__global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, int nsims)
 {
+    constexpr int kBatchTY = batch_ty(PR);
     extern __shared__ __align__(16) unsigned char smem[];
     const int s = find_sim_fused(D, nsims, blockIdx.x);
     const SimDesc &d = D[s];
@@ -305,95 +320,116 @@ __global__ __launch_bounds__(kBatchTX *kBatchTY) void kb_fused(SimDesc *D, int n
         fused_column<PR, MODEL, kBatchTX, kBatchTY, false>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
-// Planes per column of a batched simulation.  A column advances one plane at
-// a time, each plane a chain of dependent loads, arithmetic and a barrier, so
-// a launch with few columns in flight is bound by that chain's latency: the
-// z-chunk is chosen so that the group's columns fill the chip
-// (kBatchTargetBlocks blocks), within [kBatchMinTz, 48] planes (three extra
-// planes of stencil loads per chunk), and balanced over nz.
-#ifndef MCLBM_BATCH_TARGET_BLOCKS
-#define MCLBM_BATCH_TARGET_BLOCKS 1024
-#endif
-#ifndef MCLBM_BATCH_MIN_TZ
-#define MCLBM_BATCH_MIN_TZ 4
-#endif
-constexpr long long kBatchTargetBlocks = MCLBM_BATCH_TARGET_BLOCKS;
-constexpr int kBatchMinTz = MCLBM_BATCH_MIN_TZ;
-
-// plane_columns: sum over the group's one-pass sims of (nx / TX)(ny / TY) nz
-inline int batch_group_tz(long long plane_columns)
-{
-    const long long t = (plane_columns + kBatchTargetBlocks - 1) / kBatchTargetBlocks;
-    return (int)std::min<long long>(48, std::max<long long>(kBatchMinTz, t));
-}
+// Planes per column of the batched simulations of a group.  A column
+// advances one plane at a time and starts with three planes of loads, and
+// the blocks run in rounds of `resident` (the blocks the chip holds at
+// once), so the time of a step goes as rounds * (planes per chunk + 3).  The
+// chunk length is searched for the least such cost (ties: fewer blocks);
+// each simulation then balances its chunks over its nz.
 inline int batch_fused_tz(int nz, int group_tz)
 {
     const int chunks = (nz + group_tz - 1) / group_tz;
     return (nz + chunks - 1) / chunks;
 }
 
+// cols[s], nz[s]: columns per plane and planes of the group's one-pass sims
+inline int batch_group_tz(const long long *cols, const int *nz, int n, long long resident)
+{
+    int best = 1;
+    long long best_cost = -1, best_blocks = 0;
+    for (int tz = 1; tz <= 64; ++tz) {
+        long long blocks = 0;
+        int longest = 0;
+        for (int s = 0; s < n; ++s) {
+            const int t = batch_fused_tz(nz[s], tz);
+            blocks += cols[s] * ((nz[s] + t - 1) / t);
+            longest = std::max(longest, t);
+        }
+        const long long rounds = (blocks + resident - 1) / std::max<long long>(1, resident);
+        const long long cost = rounds * (longest + 3);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && blocks < best_blocks)) {
+            best = tz;
+            best_cost = cost;
+            best_blocks = blocks;
+        }
+    }
+    return best;
+}
+
+// Blocks of kb_fused<PR, MODEL> the device holds at once.
+template <int PR, int MODEL>
+long long batch_fused_resident()
+{
+    constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, batch_ty(PR)>();
+    (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_fused<PR, MODEL>, kBatchTX * batch_ty(PR), lds)
+            != hipSuccess || hipGetDevice(&dev) != hipSuccess
+        || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 256;
+    return (long long)std::max(1, per_cu) * std::max(1, cus);
+}
+
 template <int PR, int MODEL>
 void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s)
 {
-    constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, kBatchTY>();
+    constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, batch_ty(PR)>();
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((kb_fused<PR, MODEL>), dim3((unsigned)fblocks), dim3(kBatchTX * kBatchTY), lds, s, D, n);
+    hipLaunchKernelGGL((kb_fused<PR, MODEL>), dim3((unsigned)fblocks), dim3(kBatchTX * batch_ty(PR)), lds, s, D, n);
 }
 
 struct FusedShape {
     int tx, ty, tz;
+    bool ragged;   // the last column in x is an edge column
 };
 
-// Tile choice: TX = 64 when nx allows, else 32; TY = 8 when ny allows, else
-// 4; TZ planes per block.  FP64 (wide) tiles are 4 rows: half the threads, so
-// that each wave may hold its double-precision planes in up to 512 registers
-// and the LDS slot of plane z+1 stays at the FP32 size.
+// Tile choice: 64-wide rows (narrower rows split the x-shifted pushes' cache
+// lines between blocks), the last column masked when 64 does not divide nx;
+// TY = 8 when ny allows, else 4; TZ planes per block.  FP64 (wide) tiles are
+// 4 rows: half the threads, so that each wave may hold its double-precision
+// planes in up to 512 registers and the LDS slot of plane z+1 stays at the
+// FP32 size.
 inline bool fused_shape(const KParams &P, FusedShape &sh, bool wide = false)
 {
-    if (P.nx % 64 == 0) sh.tx = 64;
-    else if (P.nx % 32 == 0) sh.tx = 32;
+    sh.tx = 64;
+    sh.ragged = P.nx % 64 != 0;
+    if (!wide && P.ny % 8 == 0) sh.ty = 8;
+    else if (P.ny % 4 == 0) sh.ty = 4;
     else return false;
-    sh.ty = 0;
-    const int cand[2] = {8, 4};
-    for (int c : cand)
-        if (!(wide && c == 8) && P.ny % c == 0 && (sh.tx + 2) * (c + 2) - sh.tx * c <= sh.tx * c) {
-            sh.ty = c;
-            break;
-        }
-    if (!sh.ty) return false;
-    // z-chunk: about one block per compute unit (256 on MI355X) -- more
-    // resident blocks per XCD overflow its L2 and the halo re-reads miss
-    const long long txy = (long long)(P.nx / sh.tx) * (P.ny / sh.ty);
-    const long long tiles_z = std::max<long long>(1, (256 + txy - 1) / txy);
+    // z-chunk: at most one block per compute unit (256 on MI355X) -- more
+    // resident blocks per XCD overflow its L2 and the halo re-reads miss,
+    // and a grid just above 256 blocks runs a second, nearly empty round
+    const long long txy = (long long)((P.nx + sh.tx - 1) / sh.tx) * (P.ny / sh.ty);
+    const long long tiles_z = std::max<long long>(1, 256 / txy);
     sh.tz = (int)((P.nz + tiles_z - 1) / tiles_z);
     return true;
 }
 
-template <int PR, int MODEL, int TX, int TY>
+template <int PR, int MODEL, int TX, int TY, bool RAGGED>
 void launch_fused_shape(const KParams &P, const void *src, void *dst, unsigned *flag, int tz, hipStream_t s)
 {
-    const int tiles_x = P.nx / TX, tiles_y = P.ny / TY, tiles_z = (P.nz + tz - 1) / tz;
+    const int tiles_x = (P.nx + TX - 1) / TX, tiles_y = P.ny / TY, tiles_z = (P.nz + tz - 1) / tz;
     const dim3 grid(tiles_x * tiles_y * tiles_z), block(TX * TY);
     using S = typename Prec<PR>::S;
     constexpr int lds = fused_lds_bytes<PR, MODEL, TX, TY>();
     static bool attr_set = false;   // raise the dynamic-LDS limit once per process
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, true>,
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, true, RAGGED>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, false>,
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, false, RAGGED>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
     if (P.bc[0] == 0 && P.bc[1] == 0 && P.bc[2] == 0)
-        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, true>), grid, block, lds, s, P, (const S *)src, (S *)dst,
-                           flag, tz, tiles_x, tiles_y);
+        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, true, RAGGED>), grid, block, lds, s, P, (const S *)src,
+                           (S *)dst, flag, tz, tiles_x, tiles_y);
     else
-        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, false>), grid, block, lds, s, P, (const S *)src, (S *)dst,
-                           flag, tz, tiles_x, tiles_y);
+        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, false, RAGGED>), grid, block, lds, s, P, (const S *)src,
+                           (S *)dst, flag, tz, tiles_x, tiles_y);
 }
 
 template <int PR, int MODEL>
@@ -401,15 +437,12 @@ void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, 
 {
     FusedShape sh;
     fused_shape(P, sh, PR == 0);  // checked at create time
-    if constexpr (PR == 0) {
-        if (sh.tx == 64) launch_fused_shape<PR, MODEL, 64, 4>(P, src, dst, flag, sh.tz, s);
-        else launch_fused_shape<PR, MODEL, 32, 4>(P, src, dst, flag, sh.tz, s);
-    } else if (sh.tx == 64) {
-        if (sh.ty == 8) launch_fused_shape<PR, MODEL, 64, 8>(P, src, dst, flag, sh.tz, s);
-        else launch_fused_shape<PR, MODEL, 64, 4>(P, src, dst, flag, sh.tz, s);
-    } else {
-        if (sh.ty == 8) launch_fused_shape<PR, MODEL, 32, 8>(P, src, dst, flag, sh.tz, s);
-        else launch_fused_shape<PR, MODEL, 32, 4>(P, src, dst, flag, sh.tz, s);
+    if (sh.ty == 4) {
+        if (sh.ragged) launch_fused_shape<PR, MODEL, 64, 4, true>(P, src, dst, flag, sh.tz, s);
+        else launch_fused_shape<PR, MODEL, 64, 4, false>(P, src, dst, flag, sh.tz, s);
+    } else if constexpr (PR != 0) {
+        if (sh.ragged) launch_fused_shape<PR, MODEL, 64, 8, true>(P, src, dst, flag, sh.tz, s);
+        else launch_fused_shape<PR, MODEL, 64, 8, false>(P, src, dst, flag, sh.tz, s);
     }
 }
 

@@ -85,12 +85,12 @@ bool fused_ok(const mclbm_params &p, const Ops *ops)
     return ops && ops->has_fused() && !multirange_of(p) && fused_shape(make_kparams(p), sh, p.precision == MCLBM_FP64);
 }
 
-// The batched one-pass kernel takes kBatchTX x kBatchTY columns; a sim whose
+// The batched one-pass kernel takes 64 x batch_ty columns; a sim whose
 // kernel is pinned to the two-pass path keeps it.
 bool batch_fused_ok(const mclbm_params &p, const Ops *ops)
 {
-    return ops && ops->has_fused() && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS
-           && p.nx % kBatchTX == 0 && p.ny % kBatchTY == 0;
+    return ops && ops->batch_fused_resident() > 0 && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS
+           && p.nx % kBatchTX == 0 && p.ny % batch_ty(p.precision) == 0;
 }
 
 mclbm_status validate(const mclbm_params *p)
@@ -843,13 +843,18 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         g.fblocks = 0;
         g.oblocks = 0;
         g.any_outflow = false;
-        long long plane_columns = 0;
+        std::vector<long long> fcols;
+        std::vector<int> fnz;
         for (int idx : groups[key]) {
             const mclbm_params &q = sims[idx]->prm;
-            if (batch_fused_ok(q, sims[idx]->ops))
-                plane_columns += (long long)(q.nx / kBatchTX) * (q.ny / kBatchTY) * q.nz;
+            if (batch_fused_ok(q, sims[idx]->ops)) {
+                fcols.push_back((long long)(q.nx / kBatchTX) * (q.ny / batch_ty(q.precision)));
+                fnz.push_back(q.nz);
+            }
         }
-        const int group_tz = batch_group_tz(plane_columns);
+        const int group_tz = fcols.empty() ? 1
+                             : batch_group_tz(fcols.data(), fnz.data(), (int)fcols.size(),
+                                              g.ops->batch_fused_resident());
         for (int idx : groups[key]) {
             mclbm_sim *s = sims[idx];
             (void)hipStreamSynchronize(s->stream);
@@ -865,7 +870,7 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
             d.fblock0 = g.fblocks;
             if (batch_fused_ok(s->prm, s->ops)) {
                 d.ftz = batch_fused_tz(s->prm.nz, group_tz);
-                d.fnblocks = (long long)(s->prm.nx / kBatchTX) * (s->prm.ny / kBatchTY)
+                d.fnblocks = (long long)(s->prm.nx / kBatchTX) * (s->prm.ny / batch_ty(s->prm.precision))
                              * ((s->prm.nz + d.ftz - 1) / d.ftz);
                 g.fblocks += d.fnblocks;
             } else {

@@ -13,6 +13,8 @@ namespace mclbm {
 struct Ops {
     virtual ~Ops() {}
     virtual bool has_fused() const = 0;
+    // blocks of the batched one-pass kernel the device holds at once (0: none)
+    virtual long long batch_fused_resident() const = 0;
     // one step: src -> dst (the divergence flag reflects src)
     virtual void step(const KParams &P, const void *src, void *dst, void *field, void *gfield,
                       unsigned *flag, bool fused, hipStream_t s) const = 0;
@@ -54,10 +56,17 @@ template <class L, int PR, int MODEL, bool REP> constexpr bool fused_available()
 {
     return L::Q == 19 && !REP;
 }
+// Batched one-pass step (fused.hpp): not for the mixed-precision path (2).
+template <class L, int PR, int MODEL, bool REP> constexpr bool batch_fused_available()
+{
+    return fused_available<L, PR, MODEL, REP>() && PR != 2;
+}
 template <int PR, int MODEL>
 void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);
 template <int PR, int MODEL>
 void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s);
+template <int PR, int MODEL>
+long long batch_fused_resident();
 
 template <class L, int PR, int MODEL, bool REP>
 struct OpsT final : Ops {
@@ -65,6 +74,11 @@ struct OpsT final : Ops {
     using FT = typename Prec<PR>::F;
 
     bool has_fused() const override { return fused_available<L, PR, MODEL, REP>(); }
+    long long batch_fused_resident() const override
+    {
+        if constexpr (batch_fused_available<L, PR, MODEL, REP>()) return mclbm::batch_fused_resident<PR, MODEL>();
+        return 0;
+    }
 
     void step(const KParams &P, const void *src, void *dst, void *field, void *gfield, unsigned *flag,
               bool fused, hipStream_t s) const override
@@ -146,7 +160,7 @@ struct OpsT final : Ops {
                 hipLaunchKernelGGL((kb_gradN<L, PR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
             hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
         }
-        if constexpr (fused_available<L, PR, MODEL, REP>()) {
+        if constexpr (batch_fused_available<L, PR, MODEL, REP>()) {
             if (fblocks > 0) launch_batch_fused<PR, MODEL>(D, n, fblocks, s);
         }
         if (any_outflow && oblocks > 0)

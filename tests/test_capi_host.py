@@ -101,12 +101,14 @@ def test_unsupported_combinations(M):
     with pytest.raises(M.MclbmError) as e:
         M.state_bytes(M.make_params(lattice=M.D3Q19, model=M.SC_MP, Pi=0.01))
     assert e.value.status == -2
-    # fused needs D3Q19, no repulsion, nx % 32 == 0 and ny % 4 == 0
+    # fused needs D3Q19, no repulsion and ny % 4 == 0 (any nx: the last
+    # column in x is masked)
     with pytest.raises(M.MclbmError) as e:
         M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, kernel=M.KERNEL_FUSED))
     assert e.value.status == -2
     with pytest.raises(M.MclbmError):
-        M.state_bytes(M.make_params(lattice=M.D3Q19, nx=40, kernel=M.KERNEL_FUSED))
+        M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=30, kernel=M.KERNEL_FUSED))
+    assert M.state_bytes(M.make_params(lattice=M.D3Q19, nx=40, ny=12, kernel=M.KERNEL_FUSED)) > 0
     with pytest.raises(M.MclbmError):
         M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=18, precision=M.FP64,
                                     kernel=M.KERNEL_FUSED))

@@ -268,19 +268,20 @@ def test_fp32_mass_conservation(M):
 def test_fused_equals_two_pass_bitwise(M, prec):
     """The one-pass kernel and the two-pass kernels give bitwise identical
     populations (same node arithmetic), for every precision path, periodic
-    and walls + outflow, all three models."""
-    for bc in ((0, 0, 0), (1, 1, 2)):
+    and walls + outflow, all three models, 64-wide columns only and with a
+    masked last column (nx = 88: 64 + 24; nx = 40: one masked column)."""
+    for shape, bc in (((20, 16, 64), (0, 0, 0)), ((20, 16, 64), (1, 1, 2)), ((12, 8, 88), (0, 0, 0)),
+                      ((12, 8, 40), (1, 0, 2))):
         for model in (0, 1, 2):
-            shape = (20, 16, 64)
             kw = dict(G=-5.0, rho0_R=1.9, rho0_B=0.12) if model == 1 else dict(G_RB=1.2, A=0.02)
-            p = M.make_params(lattice=M.D3Q19, model=model, precision=prec, nx=64, ny=16, nz=20,
-                              bc=bc, **kw)
+            p = M.make_params(lattice=M.D3Q19, model=model, precision=prec, nx=shape[2], ny=shape[1],
+                              nz=shape[0], bc=bc, **kw)
             if model == 1:
                 a, b = inputs.droplet(shape, 5.0, 1.9, 0.12)
                 rR, rB = a + b, None
             else:
                 rR, rB, _ = cg_droplet_case(shape, 21)
-            say(f"[bitwise] fused vs two-pass prec={prec} bc={bc} model={model}")
+            say(f"[bitwise] fused vs two-pass prec={prec} shape={shape} bc={bc} model={model}")
             _, f1 = gpu_run(M, p, rR, rB, None, 37, kernel=1)
             _, f2 = gpu_run(M, p, rR, rB, None, 37, kernel=2)
             assert np.array_equal(f1, f2)
@@ -372,10 +373,13 @@ def test_batch_invariance_bitwise(M):
 
 
 def test_batch_one_pass_bitwise(M):
-    """Batched one-pass columns (64 x 4) beside batched two-pass sims in the
-    same batch: every sim ends bitwise equal to its solo two-pass run; every
-    precision, all three models, walls and outflow, z-chunks with a one-plane
-    last chunk (nz = 101 -> 25 x 4 + 1)."""
+    """Batched one-pass columns (64 x 8, 64 x 4 in FP64) beside batched
+    two-pass sims (nx not a multiple of 64, ny not a multiple of the column
+    height, mixed precision, repulsion, pinned two-pass, D2Q9) in the same
+    batch: every
+    sim ends bitwise equal to its solo two-pass run; every precision, all
+    three models, walls and outflow, z-chunks with a shorter last chunk (nz =
+    101 is prime: every chunk length above one leaves a remainder)."""
     def sc_mp(shape):
         a, b = inputs.droplet(shape, 3.0, 1.9, 0.12)
         return a + b, None, None
@@ -383,15 +387,16 @@ def test_batch_one_pass_bitwise(M):
     D3, F, T = M.D3Q19, M.KERNEL_FUSED, M.KERNEL_TWO_PASS
     cases = [  # params, fields, steps, expected batched kernel
         (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=16, nz=20, A=0.02), None, 23, F),
-        (M.make_params(lattice=D3, precision=M.FP64, nx=64, ny=8, nz=101, A=0.02, bc=(1, 0, 2)), None, 17, F),
+        (M.make_params(lattice=D3, precision=M.FP64, nx=64, ny=12, nz=101, A=0.02, bc=(1, 0, 2)), None, 17, F),
         (M.make_params(lattice=D3, precision=M.FP16, nx=64, ny=8, nz=16, A=0.02, bc=(0, 1, 0)), None, 21, F),
-        (M.make_params(lattice=D3, precision=M.MIXED, nx=64, ny=12, nz=16, A=0.02, rho0_B=0.01), None, 19, F),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=128, ny=16, nz=16, A=0.02, rho0_B=0.01), None, 19, T),
         (M.make_params(lattice=D3, model=M.SC_MP, precision=M.FP32, nx=64, ny=8, nz=24, G=-5.0, rho0_R=1.9,
                        rho0_B=0.12), "scmp", 25, F),
         (M.make_params(lattice=D3, model=M.SC_MC, precision=M.FP32, nx=64, ny=8, nz=16, G_RB=1.2,
                        bc=(2, 0, 1)), None, 27, F),
-        (M.make_params(lattice=D3, precision=M.FP32, nx=32, ny=16, nz=16, A=0.01), None, 29, T),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=40, ny=16, nz=16, A=0.01), None, 29, T),
         (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=6, nz=16, A=0.01), None, 13, T),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=12, nz=16, A=0.01), None, 14, T),
         (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=8, nz=16, A=0.02, Pi=0.01), None, 15, T),
         (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=8, nz=16, A=0.02, kernel=T), None, 18, T),
         (M.make_params(lattice=M.D2Q9, precision=M.FP32, nx=64, ny=32, nz=1, A=0.02), None, 31, T),
@@ -444,8 +449,8 @@ def test_batch_stops_diverged_member(M):
 
 
 def test_kernel_used_reports_the_dispatch(M):
-    """mclbm_kernel_used: fused for D3Q19 on 32/4-divisible boxes, two-pass
-    otherwise (D2Q9, ragged x or y, forced two-pass)."""
+    """mclbm_kernel_used: fused for D3Q19 when 4 divides ny (any nx), two-pass
+    otherwise (D2Q9, ny % 4 != 0, forced two-pass)."""
     def used(**kw):
         s = M.Sim(M.make_params(**kw))
         k = s.kernel_used()
@@ -458,5 +463,6 @@ def test_kernel_used_reports_the_dispatch(M):
     assert used(precision=M.FP64, **d3) == M.KERNEL_FUSED
     assert used(precision=M.FP64, lattice=M.D3Q19, nx=64, ny=18, nz=8) == M.KERNEL_TWO_PASS
     assert used(precision=M.FP32, kernel=M.KERNEL_TWO_PASS, **d3) == M.KERNEL_TWO_PASS
-    assert used(precision=M.FP32, lattice=M.D3Q19, nx=40, ny=16, nz=8) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP32, lattice=M.D3Q19, nx=40, ny=16, nz=8) == M.KERNEL_FUSED
+    assert used(precision=M.FP32, lattice=M.D3Q19, nx=64, ny=14, nz=8) == M.KERNEL_TWO_PASS
     assert used(precision=M.FP32, lattice=M.D2Q9, nx=64, ny=64, nz=1) == M.KERNEL_TWO_PASS
