@@ -153,13 +153,15 @@ def serving_leg(full: bool):
                 "D2Q9 64^2-256^2 / D3Q19 32^3-96^3, gamma 10^U(0,3), nu ratio 10^U(0,2), "
                 "sigma 10^U(-3,-1), 500-4000 steps")
     print(f"[bench] serving: {desc}", file=sys.stderr, flush=True)
+    # the full trace runs for minutes: report each finished request
+    log = (lambda s: print(s, file=sys.stderr, flush=True)) if full else None
     trace = serve.make_trace(seed=0, **kw)
-    server = serve.Server(k_steps=100)
+    server = serve.Server(k_steps=100, log=log)
     done, wall = server.run(trace)
     batched = serve.summarize(done, wall)
     print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
     trace2 = serve.make_trace(seed=0, **kw)
-    done2, wall2 = serve.serve_one_at_a_time(trace2)
+    done2, wall2 = serve.serve_one_at_a_time(trace2, log=log)
     fifo = serve.summarize(done2, wall2)
     print(f"[bench] one-at-a-time FP64: {fifo}", file=sys.stderr, flush=True)
     agree = sum(1 for a, b in zip(sorted(done, key=lambda r: r.rid), sorted(done2, key=lambda r: r.rid))
