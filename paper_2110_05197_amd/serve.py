@@ -192,16 +192,35 @@ def footprint(req: Request) -> int:
     return M.state_bytes(req.params)
 
 
+def work(req: Request) -> int:
+    """Lattice updates a request still needs."""
+    p = req.params
+    return (req.steps - req.steps_done) * p["nx"] * p["ny"] * p["nz"]
+
+
 class Server:
-    """Continuous batching: admit by free HBM, step resident sims together."""
+    """Continuous batching: admit by free HBM, step resident sims together.
+
+    policy "shared": every arrived request is admitted as soon as memory
+    allows, and all resident simulations share the GPU.
+    policy "swf" (shortest work first): arrived requests are admitted in
+    order of the lattice updates they need, while the resident lattices hold
+    at most `max_nodes` nodes (enough to keep the GPU busy); a request that
+    arrives meanwhile waits for the next completion instead of slowing the
+    running ones down.  No running simulation is preempted.
+    """
 
     def __init__(self, k_steps=100, use_graph=True, reserve_bytes=4 << 30, max_resident=512,
-                 log=None):
+                 log=None, policy="swf", max_nodes=32 << 20):
         import torch
+        if policy not in ("shared", "swf"):
+            raise ValueError(f"unknown policy {policy!r}")
         self.k = k_steps
         self.use_graph = use_graph
         self.reserve = reserve_bytes
         self.max_resident = max_resident
+        self.policy = policy
+        self.max_nodes = max_nodes if policy == "swf" else None
         self.stream = torch.cuda.Stream()
         self.log = log or (lambda *a: None)
 
@@ -218,22 +237,36 @@ class Server:
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         done = []
+        nodes = lambda r: r.params["nx"] * r.params["ny"] * r.params["nz"]
+
+        def candidates():
+            """Arrived requests in admission order."""
+            t = now()
+            arrived = [r for r in waiting if r.arrival <= t]
+            return sorted(arrived, key=work) if self.policy == "swf" else arrived
+
+        def fits(req, resident_nodes):
+            if len(resident) >= self.max_resident:
+                return False
+            if self.max_nodes is not None and resident and resident_nodes + nodes(req) > self.max_nodes:
+                return False
+            need = footprint(req) + 16 * nodes(req)
+            return self.free_bytes() - need >= self.reserve or not resident
+
         with torch.cuda.stream(self.stream):
             while waiting or resident:
-                # admit arrived requests while memory and slots allow
-                admitted_any = False
-                while waiting and waiting[0].arrival <= now() and len(resident) < self.max_resident:
-                    req = waiting[0]
-                    need = footprint(req) + 16 * (req.params["nx"] * req.params["ny"] * req.params["nz"])
-                    if self.free_bytes() - need < self.reserve and resident:
+                # admit arrived requests while memory, slots and the node budget allow
+                resident_nodes = sum(nodes(r) for (r, _, _) in resident)
+                for req in candidates():
+                    if not fits(req, resident_nodes):
                         break
-                    waiting.pop(0)
+                    waiting.remove(req)
                     sim = M.Sim(req.params, stream=self.stream)
                     rR, rB = initial_fields(req)
                     sim.init_equilibrium(rR, rB)
                     req.admitted = now()
                     resident.append([req, sim, req.steps])
-                    admitted_any = True
+                    resident_nodes += nodes(req)
                 if not resident:
                     # idle until the next arrival
                     if waiting:
@@ -241,13 +274,14 @@ class Server:
                     continue
                 batch = M.Batch([s for (_, s, _) in resident], [r for (_, _, r) in resident],
                                 stream=self.stream)
-                # replay K-step graphs until somebody finishes or new work arrives
+                # replay K-step graphs until somebody finishes or an arrival can be admitted
                 while True:
                     batch.step(self.k, use_graph=self.use_graph)
                     st, steps = batch.status()
                     finished = [i for i, s in enumerate(st) if s != M.RUNNING]
-                    arrived = bool(waiting) and waiting[0].arrival <= now()
-                    if finished or arrived:
+                    cand = candidates()
+                    admissible = bool(cand) and fits(cand[0], resident_nodes)
+                    if finished or admissible:
                         break
                 batch.close()
                 keep = []
