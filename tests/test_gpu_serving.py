@@ -88,3 +88,52 @@ def test_laplace_sweep_machinery(M):
         assert abs(m["R"] - m["R0"]) < 1.0
     e1 = {m["R0"]: m["E"] for m in res if m["gamma"] == 1}
     assert e1[12] < e1[8]
+
+
+def test_shortest_work_first_admission(M):
+    """Policy "swf": with every request arrived and a node budget that holds
+    only a few lattices, requests are admitted in order of the work they
+    need, and all of them finish with the same outcome as under "shared"."""
+    from paper_2110_05197_amd import serve
+    kw = dict(n=10, rate=1e6, seed=5, d2_sizes=(32, 48, 64), d3_sizes=(16, 32), steps_range=(100, 600))
+    trace = serve.make_trace(**kw)
+    need = {r.rid: serve.work(r) for r in trace}
+    done, _ = serve.Server(k_steps=25, policy="swf", max_nodes=3 * 32 * 32 * 32).run(trace)
+    assert len(done) == 10
+    by = sorted(done, key=lambda r: need[r.rid])
+    for a, b in zip(by, by[1:]):
+        if need[a.rid] < need[b.rid]:
+            assert a.admitted <= b.admitted, (a.rid, b.rid)
+    shared, _ = serve.Server(k_steps=25, policy="shared").run(serve.make_trace(**kw))
+    assert {r.rid: r.outcome for r in done} == {r.rid: r.outcome for r in shared}
+
+
+def test_served_one_pass_equals_solo(M):
+    """Requests on 64^3 boxes run the batched one-pass kernel when served;
+    their populations equal a solo run's, bit for bit."""
+    from paper_2110_05197_amd import serve
+    trace = serve.make_trace(n=4, rate=1e6, seed=6, d2_sizes=(32,), d3_sizes=(64,), steps_range=(60, 120))
+    for r in trace:   # colour-gradient requests of the trace's gamma and sigma, FP32, 64^3
+        p = M.make_params(lattice=M.D3Q19, model=M.CG, nx=64, ny=64, nz=64, precision=M.FP32,
+                          rho0_R=r.gamma, rho0_B=1.0, tau_R=0.8, tau_B=0.6)
+        r.params = M.params_from_sigma(p, r.sigma)
+    sims = []
+    for r in trace:
+        s = M.Sim(r.params)
+        s.init_equilibrium(*serve.initial_fields(r))
+        sims.append(s)
+    b = M.Batch(sims, [r.steps for r in trace])
+    assert b.kernels() == [M.KERNEL_FUSED] * 4
+    for _ in range(13):
+        b.step(10)
+    st, steps = b.status()
+    b.close()
+    assert st == [M.DONE] * 4
+    for r, s, n in zip(trace, sims, steps):
+        alone = M.Sim(dict(r.params, kernel=M.KERNEL_TWO_PASS))
+        alone.init_equilibrium(*serve.initial_fields(r))
+        st1, done1 = alone.step(int(n), check_every=int(n))
+        assert done1 == n
+        assert np.array_equal(alone.export_f().cpu().numpy(), s.export_f().cpu().numpy())
+        alone.close()
+        s.close()
