@@ -92,9 +92,9 @@ typedef int32_t mclbm_status;
 #define MCLBM_OUTFLOW 2
 
 /* Kernel choice for mclbm_step. */
-#define MCLBM_KERNEL_AUTO 0     /* fused where provided, else two-pass            */
+#define MCLBM_KERNEL_AUTO 0     /* fused where provided (D2Q9: from 2^19 nodes)    */
 #define MCLBM_KERNEL_TWO_PASS 1 /* density-field pass + collide/stream pass       */
-#define MCLBM_KERNEL_FUSED 2    /* one pass per step: D3Q19 CG/SC only            */
+#define MCLBM_KERNEL_FUSED 2    /* one pass per step: CG/SC without repulsion     */
 
 typedef struct mclbm_params {
     int32_t abi_version;  /* must be MCLBM_ABI_VERSION                              */
@@ -265,8 +265,9 @@ mclbm_status mclbm_plane_area(mclbm_sim *sim, int32_t axis, int32_t pos, double 
 mclbm_status mclbm_droplets(mclbm_sim *sim, int32_t max, int32_t *count, int64_t *h_sizes);
 
 /* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass:
- * D3Q19 without the repulsion or multirange forces, ny % 4 == 0, any nx) or
- * MCLBM_KERNEL_TWO_PASS.  Host only; EINVAL on NULL. */
+ * without the repulsion or multirange forces; D3Q19 with ny % 4 == 0 and any
+ * nx, D2Q9 of any size) or MCLBM_KERNEL_TWO_PASS.  Host only; EINVAL on
+ * NULL. */
 mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
 
 /* ------------------------------------------------------------------------ */

@@ -47,42 +47,60 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     return (b % 8) * (nblocks / 8) + b / 8;
 }
 
-template <int MODEL, int TX, int TY, class FT>
+// Whether a lattice has velocities along y (D2Q9Z has none: its tile rows
+// need no halo rows).
+template <class L>
+constexpr bool uses_y()
+{
+    for (int i = 0; i < L::Q; ++i)
+        if (L::cy[i] != 0) return true;
+    return false;
+}
+template <class L, int TY>
+constexpr int ring_rows() { return uses_y<L>() ? TY + 2 : TY; }
+
+template <class L, int MODEL, int TX, int TY, class FT>
 constexpr int fused_ring_bytes()
 {
-    return (4 * NField<MODEL>::n * (TX + 2) * (TY + 2) * (int)sizeof(FT) + 15) / 16 * 16;
+    return (4 * NField<MODEL>::n * (TX + 2) * ring_rows<L, TY>() * (int)sizeof(FT) + 15) / 16 * 16;
 }
-template <int PR, int MODEL, int TX, int TY>
+template <int PR, int MODEL, int TX, int TY, class L = D3Q19>
 constexpr int fused_lds_bytes()
 {
-    return fused_ring_bytes<MODEL, TX, TY, typename Prec<PR>::F>()
-           + NComp<MODEL>::n * D3Q19::Q * TX * TY * (int)sizeof(typename Prec<PR>::C);
+    return fused_ring_bytes<L, MODEL, TX, TY, typename Prec<PR>::F>()
+           + NComp<MODEL>::n * L::Q * TX * TY * (int)sizeof(typename Prec<PR>::C);
 }
 
 // One block's work: the TX x TY column at (x0, y0), planes [z0, z1).  An
 // EDGE column is the last one in x when TX does not divide nx: its first
 // w = nx - x0 threads hold nodes, the others only take part in the barriers,
-// and its +x halo is the column at x0 + w.
-template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool EDGE = false>
+// and its +x halo is the column at x0 + w.  L is the lattice of the
+// arithmetic, LA the one that places neighbours: both D3Q19, or D2Q9 and
+// D2Q9Z for a 2-D box seen as nx x 1 x ny (TY = 1, halo columns only), so
+// that a 2-D node's arithmetic is the two-pass kernels', operation for
+// operation.
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool EDGE = false, class L = D3Q19, class LA = L>
 __device__ __forceinline__ void fused_column(const KParams &P, const typename Prec<PR>::S *__restrict__ src,
                                              typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int x0, int y0,
                                              int z0, int z1, unsigned char *smem)
 {
-    using L = D3Q19;
     using C = typename Prec<PR>::C;
     using M = typename Prec<PR>::M;
     using FT = typename Prec<PR>::F;
     constexpr int Q = L::Q;
     constexpr int K = NComp<MODEL>::n;
     constexpr int NF = NField<MODEL>::n;
-    constexpr int HX = TX + 2, HY = TY + 2, PL = HX * HY, NT = TX * TY, NH = PL - NT;
+    static_assert(LA::Q == L::Q, "one velocity set");
+    constexpr bool YH = uses_y<LA>();   // halo rows y0-1 and y0+TY
+    constexpr int RY = YH ? 1 : 0;      // ring row of tile row 0
+    constexpr int HX = TX + 2, HY = ring_rows<LA, TY>(), PL = HX * HY, NT = TX * TY, NH = PL - NT;
     static_assert(NH <= NT, "halo ring larger than the block");
     // Dynamic LDS: a four-plane ring of stencil values (planes z-1, z, z+1
     // are read while plane z+2 is written), then each thread's private slot
     // holding the populations of plane z+1 (laid out [population][thread] so
     // that a wavefront's accesses are contiguous).
     FT (*lds)[NF][PL] = reinterpret_cast<FT (*)[NF][PL]>(smem);
-    C *pop = reinterpret_cast<C *>(smem + fused_ring_bytes<MODEL, TX, TY, FT>());
+    C *pop = reinterpret_cast<C *>(smem + fused_ring_bytes<LA, MODEL, TX, TY, FT>());
 
     const long long N = P.N;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -90,19 +108,20 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
-    const int my_slot = (ly + 1) * HX + (lx + 1);
+    const int my_slot = (ly + RY) * HX + (lx + 1);
     const int w = EDGE ? min(TX, nx - x0) : TX;   // nodes per row of this column
     const bool act = !EDGE || lx < w;
 
-    // halo ring node of this thread: rows y0-1 and y0+TY, then columns
-    // x0-1 and x0+w
+    // halo ring node of this thread: rows y0-1 and y0+TY (when the lattice
+    // has y velocities), then columns x0-1 and x0+w
+    constexpr int NR = YH ? 2 * HX : 0;
     int hx = 0, hy = 0;
-    if (tid < HX) { hx = tid - 1; hy = -1; }
-    else if (tid < 2 * HX) { hx = tid - HX - 1; hy = TY; }
-    else if (tid < 2 * HX + TY) { hx = -1; hy = tid - 2 * HX; }
-    else { hx = w; hy = tid - 2 * HX - TY; }
+    if (YH && tid < HX) { hx = tid - 1; hy = -1; }
+    else if (YH && tid < NR) { hx = tid - HX - 1; hy = TY; }
+    else if (tid < NR + TY) { hx = -1; hy = tid - NR; }
+    else { hx = w; hy = tid - NR - TY; }
     const bool has_h = tid < NH && hx <= w;
-    const int h_slot = (hy + 1) * HX + (hx + 1);
+    const int h_slot = (hy + RY) * HX + (hx + 1);
     const int hgx = stencil_coord(x0 + hx, nx, P.bc[0]);
     const int hgy = stencil_coord(y0 + hy, ny, P.bc[1]);
     const long long n_xy = (long long)x + (long long)nx * y;
@@ -165,8 +184,8 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
             C v[NF][Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
-                const int s = ring(z + L::cz[i]);
-                const int o = my_slot + L::cy[i] * HX + L::cx[i];
+                const int s = ring(z + LA::cz[i]);
+                const int o = my_slot + LA::cy[i] * HX + LA::cx[i];
 #pragma unroll
                 for (int a = 0; a < NF; ++a) v[a][i] = (C)lds[s][a][o];
             }
@@ -216,8 +235,8 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
             // lines and are never read again in this step: stream them past
             // the cache; the x-shifted ones share lines with the neighbouring
             // tile's stores and go through L2
-            if constexpr (PERIODIC) push_store_periodic<L, K, typename Prec<PR>::S, C, true>(P, dst, x, y, z, n, c);
-            else push_store_general<L, K, typename Prec<PR>::S, C, true>(P, dst, x, y, z, n, c);
+            if constexpr (PERIODIC) push_store_periodic<LA, K, typename Prec<PR>::S, C, true>(P, dst, x, y, z, n, c);
+            else push_store_general<LA, K, typename Prec<PR>::S, C, true>(P, dst, x, y, z, n, c);
         }
 
         // 3. stencil values of plane z+2
@@ -253,7 +272,7 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
 }
 
 // RAGGED: TX does not divide nx, and the last column in x is an edge column.
-template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool RAGGED>
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool RAGGED, class L = D3Q19, class LA = L>
 __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec<PR>::S *__restrict__ src,
                                                   typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int TZ,
                                                   int tiles_x, int tiles_y)
@@ -264,11 +283,11 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ, z1 = min(z0 + TZ, P.nz);
     if constexpr (RAGGED) {
         if (bx == tiles_x - 1) {
-            fused_column<PR, MODEL, TX, TY, PERIODIC, true>(P, src, dst, flag, x0, y0, z0, z1, smem);
+            fused_column<PR, MODEL, TX, TY, PERIODIC, true, L, LA>(P, src, dst, flag, x0, y0, z0, z1, smem);
             return;
         }
     }
-    fused_column<PR, MODEL, TX, TY, PERIODIC>(P, src, dst, flag, x0, y0, z0, z1, smem);
+    fused_column<PR, MODEL, TX, TY, PERIODIC, false, L, LA>(P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
 // Batched one-pass step: the blocks of all eligible simulations of a group
@@ -444,6 +463,55 @@ void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, 
         if (sh.ragged) launch_fused_shape<PR, MODEL, 64, 8, true>(P, src, dst, flag, sh.tz, s);
         else launch_fused_shape<PR, MODEL, 64, 8, false>(P, src, dst, flag, sh.tz, s);
     }
+}
+
+// D2Q9 one-pass step: the 2-D box as nx x 1 x ny (neighbours placed by
+// D2Q9Z, arithmetic in D2Q9), rows of
+// 256 nodes marching along y, the last row segment masked when 256 does not
+// divide nx.  Chunks of at least 8 rows, about two blocks per compute unit.
+constexpr int k2dTX = 256;
+
+inline KParams as_marching_2d(const KParams &P)
+{
+    KParams Q = P;
+    Q.ny = 1;
+    Q.nz = P.ny;
+    Q.bc[1] = 0;
+    Q.bc[2] = P.bc[1];
+    return Q;
+}
+
+template <int PR, int MODEL, bool RAGGED>
+void launch_fused2d_shape(const KParams &Q, const void *src, void *dst, unsigned *flag, hipStream_t s)
+{
+    const int tiles_x = (Q.nx + k2dTX - 1) / k2dTX;
+    const int tiles_z = std::max(1, std::min(512 / tiles_x, Q.nz / 8));
+    const int tz = (Q.nz + tiles_z - 1) / tiles_z;
+    const dim3 grid(tiles_x * ((Q.nz + tz - 1) / tz)), block(k2dTX);
+    using S = typename Prec<PR>::S;
+    constexpr int lds = fused_lds_bytes<PR, MODEL, k2dTX, 1, D2Q9Z>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, k2dTX, 1, true, RAGGED, D2Q9, D2Q9Z>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, k2dTX, 1, false, RAGGED, D2Q9, D2Q9Z>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr_set = true;
+    }
+    if (Q.bc[0] == 0 && Q.bc[2] == 0)
+        hipLaunchKernelGGL((k_fused<PR, MODEL, k2dTX, 1, true, RAGGED, D2Q9, D2Q9Z>), grid, block, lds, s, Q,
+                           (const S *)src, (S *)dst, flag, tz, tiles_x, 1);
+    else
+        hipLaunchKernelGGL((k_fused<PR, MODEL, k2dTX, 1, false, RAGGED, D2Q9, D2Q9Z>), grid, block, lds, s, Q,
+                           (const S *)src, (S *)dst, flag, tz, tiles_x, 1);
+}
+
+template <int PR, int MODEL>
+void launch_fused2d(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s)
+{
+    const KParams Q = as_marching_2d(P);
+    if (Q.nx % k2dTX) launch_fused2d_shape<PR, MODEL, true>(Q, src, dst, flag, s);
+    else launch_fused2d_shape<PR, MODEL, false>(Q, src, dst, flag, s);
 }
 
 }  // namespace mclbm

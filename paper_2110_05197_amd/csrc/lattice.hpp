@@ -49,6 +49,15 @@ struct D3Q19 {
     static constexpr double inv_len[3] = {0.0, 1.0, 0.70710678118654752440};
 };
 
+// D2Q9 seen as a 3-D lattice of a single y plane: velocities (cx, 0, cy),
+// same order and constants.  A 2-D box nx x ny is then the 3-D box
+// nx x 1 x ny with the same node numbering, and the one-pass kernel marches
+// along the 2-D y axis.
+struct D2Q9Z : D2Q9 {
+    static constexpr int cy[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int cz[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+};
+
 // Multirange neighbourhood of the two-component Shan-Chen forces (Eq.
 // pweights): the vectors of {-2..2}^3 with |c|^2 in {1, 2, 3, 4, 5, 6, 8}
 // (92 of them; belt 1 is |c|^2 <= 2, the D3Q19 set).  Both weights are even

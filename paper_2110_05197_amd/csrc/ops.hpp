@@ -51,18 +51,22 @@ inline long long outflow_count(const KParams &P)
     return c;
 }
 
-// Fused one-pass step (fused.hpp) for D3Q19 without the repulsion force.
+// Fused one-pass step (fused.hpp) for D3Q19 and D2Q9 without the repulsion
+// force.
 template <class L, int PR, int MODEL, bool REP> constexpr bool fused_available()
 {
-    return L::Q == 19 && !REP;
+    return (L::Q == 19 || L::Q == 9) && !REP;
 }
-// Batched one-pass step (fused.hpp): not for the mixed-precision path (2).
+// Batched one-pass step (fused.hpp): D3Q19, not for the mixed-precision
+// path (2).
 template <class L, int PR, int MODEL, bool REP> constexpr bool batch_fused_available()
 {
-    return fused_available<L, PR, MODEL, REP>() && PR != 2;
+    return fused_available<L, PR, MODEL, REP>() && L::Q == 19 && PR != 2;
 }
 template <int PR, int MODEL>
 void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);
+template <int PR, int MODEL>
+void launch_fused2d(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);
 template <int PR, int MODEL>
 void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s);
 template <int PR, int MODEL>
@@ -86,7 +90,8 @@ struct OpsT final : Ops {
         bool done = false;
         if constexpr (fused_available<L, PR, MODEL, REP>()) {
             if (fused) {
-                launch_fused<PR, MODEL>(P, src, dst, flag, s);
+                if constexpr (L::Q == 19) launch_fused<PR, MODEL>(P, src, dst, flag, s);
+                else launch_fused2d<PR, MODEL>(P, src, dst, flag, s);
                 done = true;
             }
         }

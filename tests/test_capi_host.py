@@ -101,10 +101,11 @@ def test_unsupported_combinations(M):
     with pytest.raises(M.MclbmError) as e:
         M.state_bytes(M.make_params(lattice=M.D3Q19, model=M.SC_MP, Pi=0.01))
     assert e.value.status == -2
-    # fused needs D3Q19, no repulsion and ny % 4 == 0 (any nx: the last
-    # column in x is masked)
+    # fused needs no repulsion, and on D3Q19 ny % 4 == 0 (any nx: the last
+    # column in x is masked); D2Q9 takes any size
+    assert M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, nx=70, ny=45, kernel=M.KERNEL_FUSED)) > 0
     with pytest.raises(M.MclbmError) as e:
-        M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, kernel=M.KERNEL_FUSED))
+        M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, Pi=0.01, kernel=M.KERNEL_FUSED))
     assert e.value.status == -2
     with pytest.raises(M.MclbmError):
         M.state_bytes(M.make_params(lattice=M.D3Q19, nx=64, ny=30, kernel=M.KERNEL_FUSED))

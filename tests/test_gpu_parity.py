@@ -75,19 +75,21 @@ def cg_droplet_case(shape, seed, gamma=1.0, lattice=1, **kw):
 # --------------------------------------------------------------------------
 # Colour gradient
 # --------------------------------------------------------------------------
-def test_cg_d2q9_fp64_static_droplet(M, orc):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_cg_d2q9_fp64_static_droplet(M, orc, kernel):
     """64x64 D2Q9 droplet R = 16, A = 0.01, tau = 1, beta = 0.7, FP64."""
     p = M.make_params(lattice=M.D2Q9, model=M.CG, precision=M.FP64, nx=64, ny=64, nz=1, A=0.01)
     rR, rB = inputs.droplet((1, 64, 64), 16.0)
-    compare(M, orc, p, rR, rB, None, 100, 1e-10, label="cg-d2q9-config1")
+    compare(M, orc, p, rR, rB, None, 100, 1e-10, kernel=kernel, label="cg-d2q9-config1")
 
 
-def test_cg_d2q9_fp64_ragged_moving(M, orc):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_cg_d2q9_fp64_ragged_moving(M, orc, kernel):
     shape = (1, 45, 70)
     p = M.make_params(lattice=M.D2Q9, precision=M.FP64, nx=70, ny=45, nz=1, A=0.03, tau_R=0.7,
                       tau_B=1.2, rho0_B=0.1)
     rR, rB, u = cg_droplet_case(shape, 11, gamma=10.0, lattice=0)
-    compare(M, orc, p, rR, rB, u, 100, 1e-10, label="cg-d2q9-ragged")
+    compare(M, orc, p, rR, rB, u, 100, 1e-10, kernel=kernel, label="cg-d2q9-ragged")
 
 
 def test_cg_d3q19_fp64_ragged_density_ratio(M, orc):
@@ -168,11 +170,12 @@ def test_cg_walls_outflow(M, orc, prec, kernel, tol):
     compare(M, orc, p, rR, rB, u, 100, tol, kernel=kernel, label="cg-walls-outflow")
 
 
-def test_cg_d2q9_walls(M, orc):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_cg_d2q9_walls(M, orc, kernel):
     shape = (1, 30, 50)
     p = M.make_params(lattice=M.D2Q9, precision=M.FP64, nx=50, ny=30, nz=1, bc=(2, 1, 0), A=0.02)
     rR, rB, u = cg_droplet_case(shape, 17, lattice=0)
-    compare(M, orc, p, rR, rB, u, 100, 1e-10, label="cg-d2q9-walls")
+    compare(M, orc, p, rR, rB, u, 100, 1e-10, kernel=kernel, label="cg-d2q9-walls")
 
 
 # --------------------------------------------------------------------------
@@ -284,6 +287,28 @@ def test_fused_equals_two_pass_bitwise(M, prec):
             say(f"[bitwise] fused vs two-pass prec={prec} shape={shape} bc={bc} model={model}")
             _, f1 = gpu_run(M, p, rR, rB, None, 37, kernel=1)
             _, f2 = gpu_run(M, p, rR, rB, None, 37, kernel=2)
+            assert np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("prec", [1, 0, 2, 3])
+def test_fused_equals_two_pass_bitwise_d2q9(M, prec):
+    """D2Q9 one-pass kernel (rows of 256 marching along y; the box seen as
+    nx x 1 x ny) against the two-pass kernels, bitwise: every precision, all
+    three models, periodic, walls + outflow, full and masked row segments."""
+    for shape, bc in (((1, 40, 512), (0, 0, 0)), ((1, 33, 300), (0, 0, 0)), ((1, 48, 300), (1, 2, 0)),
+                      ((1, 20, 64), (2, 1, 0))):
+        for model in (0, 1, 2):
+            kw = dict(G=-5.0, rho0_R=1.9, rho0_B=0.12) if model == 1 else dict(G_RB=1.2, A=0.02)
+            p = M.make_params(lattice=M.D2Q9, model=model, precision=prec, nx=shape[2], ny=shape[1], nz=1,
+                              bc=bc, **kw)
+            if model == 1:
+                a, b = inputs.droplet(shape, 6.0, 1.9, 0.12)
+                rR, rB = a + b, None
+            else:
+                rR, rB, _ = cg_droplet_case(shape, 27, lattice=0)
+            say(f"[bitwise d2q9] fused vs two-pass prec={prec} shape={shape} bc={bc} model={model}")
+            _, f1 = gpu_run(M, p, rR, rB, None, 41, kernel=1)
+            _, f2 = gpu_run(M, p, rR, rB, None, 41, kernel=2)
             assert np.array_equal(f1, f2)
 
 
@@ -449,8 +474,10 @@ def test_batch_stops_diverged_member(M):
 
 
 def test_kernel_used_reports_the_dispatch(M):
-    """mclbm_kernel_used: fused for D3Q19 when 4 divides ny (any nx), two-pass
-    otherwise (D2Q9, ny % 4 != 0, forced two-pass)."""
+    """mclbm_kernel_used: fused for D3Q19 when 4 divides ny (any nx) and for
+    D2Q9 from 2^19 nodes (any size when requested), two-pass otherwise (D3Q19
+    with ny % 4 != 0, the repulsion force, small D2Q9 boxes, forced
+    two-pass)."""
     def used(**kw):
         s = M.Sim(M.make_params(**kw))
         k = s.kernel_used()
@@ -465,4 +492,9 @@ def test_kernel_used_reports_the_dispatch(M):
     assert used(precision=M.FP32, kernel=M.KERNEL_TWO_PASS, **d3) == M.KERNEL_TWO_PASS
     assert used(precision=M.FP32, lattice=M.D3Q19, nx=40, ny=16, nz=8) == M.KERNEL_FUSED
     assert used(precision=M.FP32, lattice=M.D3Q19, nx=64, ny=14, nz=8) == M.KERNEL_TWO_PASS
-    assert used(precision=M.FP32, lattice=M.D2Q9, nx=64, ny=64, nz=1) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP32, lattice=M.D2Q9, nx=1024, ny=512, nz=1) == M.KERNEL_FUSED
+    assert used(precision=M.FP64, lattice=M.D2Q9, nx=1000, ny=700, nz=1) == M.KERNEL_FUSED
+    # small 2-D boxes: the automatic choice is two-pass, the one-pass kernel on request
+    assert used(precision=M.FP32, lattice=M.D2Q9, nx=512, ny=512, nz=1) == M.KERNEL_TWO_PASS
+    assert used(precision=M.FP32, lattice=M.D2Q9, nx=64, ny=64, nz=1, kernel=M.KERNEL_FUSED) == M.KERNEL_FUSED
+    assert used(precision=M.FP32, lattice=M.D2Q9, nx=2048, ny=2048, nz=1, Pi=0.01) == M.KERNEL_TWO_PASS
