@@ -304,7 +304,10 @@ static double guo_source(const orc_lattice *L, int i, double om, const double u[
 /* CG repulsion force (Eq. repForce, Eqs. normal1/normal2).                   */
 /* reading: psi_rep = (1 - |rho^N|)^chi so that the force vanishes in the     */
 /* bulk and grows as two interfaces approach; a normal is zero where          */
-/* |grad rho^N| <= g_min; H(0) = 0.                                            */
+/* |grad rho^N| <= g_min; H(0) = 0.  Direction: the text of section 2.3 sets  */
+/* an outward (repulsive) force on the nodes around an extremum of rho^N,     */
+/* while the printed sum, with n'_i taken at x + c_i, points from each such   */
+/* node toward the extremum; the force is applied outward, as minus that sum. */
 /* ------------------------------------------------------------------------ */
 static void repulsion_pass(const orc_params *p, const orc_lattice *L, const double *rhoN,
                            const double *gradN, double *F)
@@ -335,7 +338,7 @@ static void repulsion_pass(const orc_params *p, const orc_lattice *L, const doub
             }
         }
         double psi_rep = pow(1.0 - fabs(rhoN[n]), p->chi);
-        for (int d = 0; d < 3; ++d) F[d * N + n] = p->Pi * psi_rep * acc[d];
+        for (int d = 0; d < 3; ++d) F[d * N + n] = -p->Pi * psi_rep * acc[d];
     }
 }
 

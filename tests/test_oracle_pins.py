@@ -550,11 +550,12 @@ def test_sc_two_component_demixing_threshold(orc, G_RB, grows):
 # physics unpinned, properties only.
 # --------------------------------------------------------------------------
 def test_repulsion_force_properties(orc):
-    """Thin blue films across x separate red slabs: the force pushes the film
-    fluid toward the film centre (a disjoining pressure), is mirror-
-    antisymmetric about it, and decays with the proximity measure
-    1 - |rho^N|: at a red maximum where |rho^N| = 0.99 it is far weaker than
-    in the film, where |rho^N| = 0.76."""
+    """Thin blue films across x separate red slabs: the force pushes the
+    nodes beside the film centre outward, away from it and toward the two
+    interfaces (the repulsion of section 2.3), is mirror-antisymmetric about
+    the centre, and decays with the proximity measure 1 - |rho^N|: at a red
+    maximum where |rho^N| = 0.99 it is far weaker than in the film, where
+    |rho^N| = 0.76."""
     nx = 32
     shape = (1, 3, nx)
     x = np.arange(nx, dtype=float)
@@ -569,7 +570,7 @@ def test_repulsion_force_properties(orc):
     Fx = F[0, 0, 1]
     assert np.allclose(F[1], 0, atol=1e-15)
     assert np.allclose(Fx[:16], -Fx[15::-1], atol=1e-15)      # mirror about x = 7.5
-    assert Fx[7] > 0 and Fx[8] < 0                            # toward the film centre
+    assert Fx[7] < 0 and Fx[8] > 0                            # away from the film centre
     film = abs(Fx[7])
     assert abs(Fx[15]) < 0.1 * film and abs(Fx[16]) < 0.1 * film
     assert abs(Fx[15]) > 0                                    # defined, small, at the red max
