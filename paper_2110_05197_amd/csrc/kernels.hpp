@@ -281,7 +281,8 @@ __device__ __forceinline__ void gradN_body(const KParams &P, const typename Prec
     for (int d = 0; d < 3; ++d) gfield[d * P.N + n] = (typename Prec<PR>::F)(C(3) * s[d]);
 }
 
-// Repulsion force at (x, y, z) (Eq. repForce; psi_rep = (1 - |rho^N|)^chi).
+// Repulsion force at (x, y, z) (Eq. repForce; psi_rep = (1 - |rho^N|)^chi;
+// applied outward from the extremum of rho^N, as section 2.3 describes).
 template <class L, class C, class FT>
 __device__ __forceinline__ void repulsion_force(const KParams &P, const FT *__restrict__ field,
                                                 const FT *__restrict__ gfield, int x, int y, int z,
@@ -309,10 +310,12 @@ __device__ __forceinline__ void repulsion_force(const KParams &P, const FT *__re
             for (int d = 0; d < 3; ++d) acc[d] += (nc * nv[d] + npc * np[d]) * il;
         }
     }
+    // outward, away from the extremum of rho^N between the interfaces: minus
+    // the sum above, which points toward it
     const C rn = (C)field[2 * N + n];
     const C psi = pow(C(1) - fabs(rn), (C)P.chi);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) F[d] = (C)P.Pi * psi * acc[d];
+    for (int d = 0; d < 3; ++d) F[d] = -(C)P.Pi * psi * acc[d];
 }
 
 // ---------------------------------------------------------------------------

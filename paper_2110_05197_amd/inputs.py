@@ -113,6 +113,24 @@ def random_droplets(shape, count, rmin, rmax, seed, rho0_R=1.0, rho0_B=1.0, widt
     return rR, rB, placed
 
 
+def droplet_pair(shape, radius, separation, speed, rho0_R=1.0, rho0_B=1.0, width=2.0):
+    """Two equal spheres on the x axis through the box centre, centres
+    ``separation`` apart, moving towards each other at ``speed``: u_x is
+    +speed inside the left droplet and -speed inside the right one, each
+    weighted by that droplet's red fraction (1 + phi) / 2.  Returns
+    (rho_R, rho_B, u)."""
+    nz, ny, nx = shape
+    x, y, z = _grid(shape)
+    cx, cy, cz = (nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0
+    r2 = (y - cy) ** 2 + (z - cz) ** 2
+    dl = radius - np.sqrt((x - (cx - separation / 2.0)) ** 2 + r2)
+    dr = radius - np.sqrt((x - (cx + separation / 2.0)) ** 2 + r2)
+    rR, rB = fields_from_distance(np.maximum(dl, dr), rho0_R, rho0_B, width)
+    u = np.zeros((3,) + tuple(shape))
+    u[0] = speed * 0.5 * (1.0 + np.tanh(dl / width)) - speed * 0.5 * (1.0 + np.tanh(dr / width))
+    return rR, rB, u
+
+
 def jet(shape, radius, wavelength, amplitude, phase=0.0, rho0_R=1.0, rho0_B=1.0, width=2.0):
     """Cylinder along z with radius R (1 + a sin(2 pi z / lambda + phase))."""
     nz, ny, nx = shape

@@ -346,3 +346,34 @@ def test_rayleigh_plateau_criterion(M):
         n, sizes = result[lam]
         assert n == 2 and sizes[1] < 0.05 * sizes[0]
     assert result[96][1][1] < result[128][1][1]
+
+
+def test_droplet_collision_repulsion(M):
+    """Head-on collision of the droplet-collision section: R0 = 14, centres
+    32 apart on x, each moving towards the other at |v_x|, rho_R = rho_B =
+    1.36, tau = 1, sigma = 0.023 (A from Eq. sigmaA), 128x64x64 periodic,
+    FP32, CG with the interface repulsion (chi = 1).  Without repulsion the
+    droplets coalesce at |v_x| = 0.06; with Pi = 1.05e-2 (tuned, as the paper
+    tunes Pi, for the reading psi_rep = (1 - |rho^N|)^chi) they stay apart at
+    0.06 and coalesce at 0.07, and the bridge radius of the coalesced drop
+    (centre plane) approaches the radius 2^(1/3) R0 of the merged sphere."""
+    shape = (64, 64, 128)
+    out = {}
+    for Pi, v in ((0.0, 0.06), (1.05e-2, 0.06), (1.05e-2, 0.07)):
+        p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=128, ny=64, nz=64, rho0_R=1.36,
+                          rho0_B=1.36, tau_R=1.0, tau_B=1.0, Pi=Pi, chi=1.0)
+        p = M.params_from_sigma(p, 0.023)
+        rR, rB, u = inputs.droplet_pair(shape, 14.0, 32.0, v, 1.36, 1.36)
+        s = M.Sim(p)
+        s.init_equilibrium(rR, rB, u)
+        st, _ = s.step(2500, check_every=500)
+        assert st == M.OK
+        n, _ = s.droplets(8)
+        rc = math.sqrt(s.plane_area(0, 63) / math.pi)
+        s.close()
+        out[(Pi, v)] = (n, rc)
+        say(f"[collision] Pi={Pi:g} v={v}: {n} droplet(s), bridge radius {rc:.2f}")
+    RD = 14.0 * 2 ** (1 / 3)
+    assert out[(0.0, 0.06)][0] == 1
+    assert out[(1.05e-2, 0.06)][0] == 2 and out[(1.05e-2, 0.06)][1] < 3.0
+    assert out[(1.05e-2, 0.07)][0] == 1 and abs(out[(1.05e-2, 0.07)][1] - RD) < 0.05 * RD
