@@ -98,10 +98,12 @@ bool auto_prefers_fused(const mclbm_params &p)
 
 // The batched one-pass kernel takes 64 x batch_ty columns; a sim whose
 // kernel is pinned to the two-pass path keeps it.
-bool batch_fused_ok(const mclbm_params &p, const Ops *ops)
+// `resident`: the group's Ops::batch_fused_resident() (0: no batched
+// one-pass kernel for this lattice, model and precision).
+bool batch_fused_ok(const mclbm_params &p, long long resident)
 {
-    return ops && ops->batch_fused_resident() > 0 && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS
-           && p.nx % kBatchTX == 0 && p.ny % batch_ty(p.precision) == 0;
+    return resident > 0 && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS && p.nx % kBatchTX == 0
+           && p.ny % batch_ty(p.precision) == 0;
 }
 
 mclbm_status validate(const mclbm_params *p)
@@ -855,18 +857,18 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         g.fblocks = 0;
         g.oblocks = 0;
         g.any_outflow = false;
+        const long long resident = g.ops->batch_fused_resident();
         std::vector<long long> fcols;
         std::vector<int> fnz;
         for (int idx : groups[key]) {
             const mclbm_params &q = sims[idx]->prm;
-            if (batch_fused_ok(q, sims[idx]->ops)) {
+            if (batch_fused_ok(q, resident)) {
                 fcols.push_back((long long)(q.nx / kBatchTX) * (q.ny / batch_ty(q.precision)));
                 fnz.push_back(q.nz);
             }
         }
         const int group_tz = fcols.empty() ? 1
-                             : batch_group_tz(fcols.data(), fnz.data(), (int)fcols.size(),
-                                              g.ops->batch_fused_resident());
+                             : batch_group_tz(fcols.data(), fnz.data(), (int)fcols.size(), resident);
         for (int idx : groups[key]) {
             mclbm_sim *s = sims[idx];
             (void)hipStreamSynchronize(s->stream);
@@ -880,7 +882,7 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
             d.flag = s->d_flag;
             d.block0 = g.blocks;
             d.fblock0 = g.fblocks;
-            if (batch_fused_ok(s->prm, s->ops)) {
+            if (batch_fused_ok(s->prm, resident)) {
                 d.ftz = batch_fused_tz(s->prm.nz, group_tz);
                 d.fnblocks = (long long)(s->prm.nx / kBatchTX) * (s->prm.ny / batch_ty(s->prm.precision))
                              * ((s->prm.nz + d.ftz - 1) / d.ftz);
