@@ -101,7 +101,8 @@ typedef struct mclbm_params {
     int32_t lattice;      /* MCLBM_D2Q9 or MCLBM_D3Q19                              */
     int32_t model;        /* MCLBM_CG, MCLBM_SC_MP, MCLBM_SC_MC                     */
     int32_t precision;    /* MCLBM_FP64 ... MCLBM_FP16                              */
-    int32_t nx, ny, nz;   /* lattice size; nz = 1 on D2Q9; each >= 2 otherwise      */
+    int32_t nx, ny, nz;   /* lattice size; nz = 1 on D2Q9; each >= 2 otherwise;     */
+                          /* nx * ny * nz < 2^31 (EUNSUPPORTED beyond)              */
     int32_t bc[3];        /* boundary type per axis x, y, z                         */
     int32_t enhanced_eq;  /* CG: 1 = enhanced equilibrium terms of Eq. equiliCG    */
     int32_t kernel;       /* MCLBM_KERNEL_*                                         */

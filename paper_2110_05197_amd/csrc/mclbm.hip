@@ -118,7 +118,9 @@ mclbm_status validate(const mclbm_params *p)
     if (p->lattice == MCLBM_D2Q9 && p->nz != 1) return fail(MCLBM_EINVAL, "D2Q9 needs nz == 1");
     if (p->lattice == MCLBM_D3Q19 && p->nz < 2) return fail(MCLBM_EINVAL, "D3Q19 needs nz >= 2");
     const long long N = (long long)p->nx * p->ny * p->nz;
-    if (N > (1LL << 34)) return fail(MCLBM_EINVAL, "lattice too large");
+    // the step kernels address a node within a population array with a 32-bit
+    // offset, and the periodic push's face corrections are ints
+    if (N >= (1LL << 31)) return fail(MCLBM_EUNSUPPORTED, "lattices of 2^31 nodes or more are not supported");
     for (int d = 0; d < 3; ++d)
         if (p->bc[d] < 0 || p->bc[d] > 2) return fail(MCLBM_EINVAL, "bad boundary type on axis %d", d);
     if (p->lattice == MCLBM_D2Q9 && p->bc[2] != MCLBM_PERIODIC) return fail(MCLBM_EINVAL, "D2Q9: bc[2] must be periodic");

@@ -120,6 +120,19 @@ def test_unsupported_combinations(M):
                                            kernel=M.KERNEL_FUSED)) > 0
 
 
+def test_node_count_limit(M):
+    """The step kernels use 32-bit node offsets: 2^31 nodes or more are
+    refused (EUNSUPPORTED) before any memory is asked for, also for storage
+    small enough to fit in HBM (FP16 single-component D2Q9 at 2^31 nodes is
+    about 150 GB with both buffers)."""
+    for kw in (dict(lattice=M.D3Q19, nx=2048, ny=1024, nz=1024),
+               dict(lattice=M.D2Q9, model=M.SC_MP, precision=M.FP16, nx=65536, ny=32768, nz=1)):
+        with pytest.raises(M.MclbmError) as e:
+            M.state_bytes(M.make_params(**kw))
+        assert e.value.status == -2
+    assert M.state_bytes(M.make_params(lattice=M.D3Q19, nx=2048, ny=1024, nz=1023)) > 0
+
+
 def test_d2q9_rejects_z_boundaries(M):
     with pytest.raises(M.MclbmError):
         M.state_bytes(M.make_params(lattice=M.D2Q9, nz=1, bc=(0, 0, 1)))
