@@ -23,7 +23,6 @@ constexpr int kRedBlocks = 1024;
 
 struct EpsTable { double e[10]; };
 
-template <class T> __device__ __forceinline__ T ldf(const T *p) { return *p; }
 
 // ---------------------------------------------------------------------------
 // Loads and stores of one node's populations.
