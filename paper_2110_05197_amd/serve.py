@@ -130,12 +130,16 @@ def sc_coupling_for_ratio(gamma: float) -> float:
 
 def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 512),
                d3_sizes=(64, 80, 96, 112, 128, 144, 160), steps_range=(1000, 20000),
-               precisions=(1, 2)):
+               precisions=(1, 2), precision_rule="gamma"):
     """Seeded request trace: Poisson arrivals at `rate` per second; model CG
     or SC (p = 1/2); droplet (R = L/4) or ligament (R = L/8, aspect 5, capped
     to 0.8 L); D2Q9 or D3Q19 (p = 1/2) with L from the size lists; density
     ratio 10^U(0,3), viscosity ratio 10^U(0,2), sigma 10^U(-3,-1); steps
-    U{steps_range}; FP32 or mixed storage."""
+    U{steps_range}; FP32 or mixed storage.  precision_rule "gamma": FP32 below
+    density ratio 100 and mixed from 100 on (the light-phase FP64 arithmetic
+    of the mixed path is what high density ratios need); "random": drawn from
+    `precisions`.  The draw is made under both rules, so the traces differ
+    in precision only."""
     import paper_2110_05197_amd as M
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -151,6 +155,10 @@ def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 5
         sigma = 10 ** rng.uniform(-3, -1)
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
         prec = int(rng.choice(precisions))
+        if precision_rule == "gamma":
+            prec = M.MIXED if gamma >= 100.0 else M.FP32
+        elif precision_rule != "random":
+            raise ValueError(f"unknown precision rule {precision_rule!r}")
         lattice = M.D3Q19 if d3 else M.D2Q9
         base = dict(lattice=lattice, nx=L, ny=L, nz=L if d3 else 1, precision=prec)
         # heavy fluid more viscous: nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)

@@ -66,6 +66,18 @@ def test_trace_is_seeded():
     assert all(x.arrival < y.arrival for x, y in zip(a, a[1:]))
 
 
+def test_trace_precision_rule():
+    """Rule "gamma": mixed storage exactly for density ratios >= 100; the
+    rest of the trace is the one the "random" rule draws."""
+    import paper_2110_05197_amd as M
+    g = serve.make_trace(seed=5, n=60)
+    r = serve.make_trace(seed=5, n=60, precision_rule="random")
+    assert all(x.params["precision"] == (M.MIXED if x.gamma >= 100 else M.FP32) for x in g)
+    assert {x.params["precision"] for x in r} == {M.FP32, M.MIXED}
+    strip = lambda d: {k: v for k, v in d.items() if k != "precision"}
+    assert all(strip(a.params) == strip(b.params) and a.arrival == b.arrival for a, b in zip(g, r))
+
+
 def test_initial_fields_sc_at_coexistence():
     tr = serve.make_trace(seed=0, n=40, d2_sizes=(64,), d3_sizes=(32,))
     sc = [r for r in tr if r.params["model"] == 1]
