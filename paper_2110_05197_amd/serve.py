@@ -215,7 +215,9 @@ class Server:
     order of the lattice updates they need, while the resident lattices hold
     at most `max_nodes` nodes (enough to keep the GPU busy); a request that
     arrives meanwhile waits for the next completion instead of slowing the
-    running ones down.  No running simulation is preempted.
+    running ones down.  No running simulation is preempted.  As with any
+    shortest-first order, a long request waits while shorter ones keep
+    arriving; on a finite trace it runs once they are served.
     """
 
     def __init__(self, k_steps=100, use_graph=True, reserve_bytes=4 << 30, max_resident=512,
