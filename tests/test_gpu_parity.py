@@ -312,6 +312,28 @@ def test_fused_equals_two_pass_bitwise_d2q9(M, prec):
             assert np.array_equal(f1, f2)
 
 
+@pytest.mark.parametrize("lattice,shape,bc", [
+    (1, (2, 4, 2), (0, 0, 0)), (1, (2, 4, 3), (1, 0, 2)), (1, (3, 8, 65), (0, 1, 0)),
+    (1, (5, 4, 130), (2, 0, 1)), (0, (1, 2, 2), (0, 0, 0)), (0, (1, 3, 257), (1, 2, 0)),
+    (0, (1, 1000, 3), (0, 0, 0)), (0, (1, 9, 513), (2, 1, 0))])
+def test_fused_degenerate_boxes(M, orc, lattice, shape, bc):
+    """Boxes of two or three nodes along an axis (halos that wrap onto the
+    column itself, a single masked column or row segment), long thin boxes
+    and a one-node edge segment: the one-pass kernel equals the two-pass
+    kernels bit for bit (FP32) and the FP64 oracle to 1e-10 (FP64)."""
+    nz, ny, nx = shape
+    say(f"[degenerate] lattice={lattice} shape={shape} bc={bc}")
+    for prec in (1, 0):
+        p = M.make_params(lattice=lattice, precision=prec, nx=nx, ny=ny, nz=nz, bc=bc, A=0.02)
+        rR, rB, u = cg_droplet_case(shape, 31, lattice=lattice)
+        if prec == 1:
+            _, f1 = gpu_run(M, p, rR, rB, u, 23, kernel=1)
+            _, f2 = gpu_run(M, p, rR, rB, u, 23, kernel=2)
+            assert np.array_equal(f1, f2)
+        else:
+            compare(M, orc, p, rR, rB, u, 23, 1e-10, kernel=2, label="degenerate")
+
+
 def test_checkpoint_restore_bitwise(M):
     shape = (16, 16, 32)
     p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=32, ny=16, nz=16, A=0.02)
