@@ -462,6 +462,12 @@ struct mclbm_batch {
         bool any_outflow;
     };
     std::vector<Group> groups;
+    // groups after the first run on side streams, forked from and joined
+    // back to `stream` every step, so that the groups' kernels overlap (in a
+    // captured graph: parallel branches)
+    std::vector<hipStream_t> side;
+    hipEvent_t fork;
+    std::vector<hipEvent_t> join;
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_k;
@@ -809,8 +815,12 @@ mclbm_status mclbm_batch_destroy(mclbm_batch *b)
 {
     if (!b) return MCLBM_OK;
     (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t s : b->side) (void)hipStreamSynchronize(s);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     for (mclbm_sim *s : b->sims) s->in_batch = false;
@@ -908,6 +918,21 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         }
         b->groups.push_back(g);
     }
+    if (b->groups.size() > 1) {
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (size_t g = 1; g < b->groups.size() && e == hipSuccess; ++g) {
+            hipStream_t s = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);   // default priority
+            if (e == hipSuccess) b->side.push_back(s);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) b->join.push_back(ev);
+        }
+        if (e != hipSuccess) {
+            mclbm_batch_destroy(b);
+            return fail(MCLBM_EDEVICE, "batch streams: %s", hipGetErrorString(e));
+        }
+    }
     for (int i = 0; i < n; ++i) {
         e = hipMemsetAsync(sims[i]->d_flag, 0, sizeof(unsigned), b->stream);
         if (e != hipSuccess) break;
@@ -923,15 +948,32 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
     return MCLBM_OK;
 }
 
-static void batch_enqueue(mclbm_batch *b, int k)
+// One batch step per iteration: fork the side streams from `stream`, each
+// group's kernels on its stream, join, then the per-sim advance.  Returns the
+// first error of the stream and event calls.
+static hipError_t batch_enqueue(mclbm_batch *b, int k)
 {
     const int n = (int)b->sims.size();
+    const size_t G = b->groups.size();
+    hipError_t e = hipSuccess;
+    auto keep = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     for (int t = 0; t < k; ++t) {
-        for (const auto &g : b->groups)
-            g.ops->batch_step(b->d_desc + g.first, g.count, g.blocks, g.fblocks, g.oblocks, g.any_outflow,
-                              b->stream);
+        if (G > 1) {
+            keep(hipEventRecord(b->fork, b->stream));
+            for (size_t g = 1; g < G; ++g) keep(hipStreamWaitEvent(b->side[g - 1], b->fork, 0));
+        }
+        for (size_t g = 0; g < G; ++g) {
+            const auto &gr = b->groups[g];
+            gr.ops->batch_step(b->d_desc + gr.first, gr.count, gr.blocks, gr.fblocks, gr.oblocks,
+                               gr.any_outflow, g == 0 ? b->stream : b->side[g - 1]);
+        }
+        for (size_t g = 1; g < G; ++g) {
+            keep(hipEventRecord(b->join[g - 1], b->side[g - 1]));
+            keep(hipStreamWaitEvent(b->stream, b->join[g - 1], 0));
+        }
         hipLaunchKernelGGL(kb_advance, dim3((n + 63) / 64), dim3(64), 0, b->stream, b->d_desc, n);
     }
+    return e;
 }
 
 mclbm_status mclbm_batch_step(mclbm_batch *b, int32_t ksteps, int32_t use_graph)
@@ -940,16 +982,21 @@ mclbm_status mclbm_batch_step(mclbm_batch *b, int32_t ksteps, int32_t use_graph)
     if (ksteps == 0) return MCLBM_OK;
     if (use_graph && !b->stream) return fail(MCLBM_EINVAL, "graph capture needs a non-null stream");
     if (!use_graph) {
-        batch_enqueue(b, ksteps);
+        const hipError_t e = batch_enqueue(b, ksteps);
+        if (e != hipSuccess) return fail(MCLBM_EDEVICE, "batch step: %s", hipGetErrorString(e));
         return launched("batch step");
     }
     if (!b->exec || b->graph_k != ksteps) {
         if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
         if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
         MCLBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        batch_enqueue(b, ksteps);
+        const hipError_t eq = batch_enqueue(b, ksteps);
         hipError_t e = hipStreamEndCapture(b->stream, &b->graph);
-        if (e != hipSuccess) return fail(MCLBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        if (e == hipSuccess) e = eq;
+        if (e != hipSuccess) {
+            if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+            return fail(MCLBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
         MCLBM_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->graph_k = ksteps;
     }
