@@ -282,7 +282,10 @@ mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
 /* Group sims (created as above, initialised, on any streams) into a batch
  * that advances them together on `stream`: one launch per kernel per group of
  * equal (lattice, model, precision), with per-lattice parameters, sizes and
- * boundaries in device descriptors.  target_steps[s] (host, n values) is the
+ * boundaries in device descriptors.  Groups after the first run on streams
+ * the batch creates (default priority), forked from and joined back to
+ * `stream` within every step, so that all work of a step is ordered on
+ * `stream`.  target_steps[s] (host, n values) is the
  * number of further steps sim s should take; a sim stops when it reaches
  * its target or diverges.  Sims must not be stepped on their own while in a
  * batch.  D3Q19 sims that have a one-pass kernel (no repulsion force, no
