@@ -205,12 +205,34 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=100_000)
     ap.add_argument("--model", default="CG", choices=sorted(MODELS))
     ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
+    ap.add_argument("--study", choices=["rp", "ligament"],
+                    help="physics run of a paper case instead of the benchmark: the Rayleigh-Plateau jet "
+                         "(CG and SC, breakup and satellites) or the density-ratio-1000 ligament "
+                         "(mixed and FP16 storage)")
+    ap.add_argument("--study-steps", type=int, default=None)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.size)
         return
     if args.stream_probe:
         stream_probe(args.size)
+        return
+    if args.study:
+        import paper_2110_05197_amd as M
+        from paper_2110_05197_amd import studies
+        log = lambda *a: print(*a, file=sys.stderr, flush=True)
+        if args.study == "rp":
+            steps = args.study_steps or 30000
+            sc = studies.sc_mc_sigma(M)
+            log(f"[rp] Shan-Chen sigma {sc['sigma']:.4f} (Laplace, R = {sc['radius']:.2f})")
+            out = dict(study="rayleigh-plateau", sc_mc_sigma=sc,
+                       runs=[studies.rayleigh_plateau(M, m, steps=steps, sigma=sc["sigma"], log=log)
+                             for m in ("CG", "SC_MC")])
+        else:
+            steps = args.study_steps or 40000
+            out = dict(study="ligament", runs=[studies.ligament(M, prec, steps=steps, log=log)
+                                               for prec in (M.MIXED, M.FP16)])
+        print(json.dumps(out))
         return
     if args.sweep:
         from paper_2110_05197_amd import sweeps

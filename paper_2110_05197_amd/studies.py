@@ -1,0 +1,200 @@
+"""Physics runs of the paper's breakup and high-density-ratio cases on the GPU,
+reporting the quantities the paper measures on them.
+
+* ``rayleigh_plateau(model)``: the periodic jet of the breakup section
+  (128 x 128 x 512, axis along z, R0 = 12, sinusoidal radius perturbation of
+  0.1 R0, wavelength drawn in [9 R0, 12 R0] and made commensurate with the
+  box), colour gradient or two-component Shan-Chen at density ratio 1, FP32,
+  the colour-gradient sigma set to the Shan-Chen one measured by
+  ``sc_mc_sigma`` (matched surface tension).
+  Every ``every`` steps the droplet counter gives the number of droplets and
+  their node counts: the breakup time is the first sample with more than one
+  droplet; satellites are the droplets below a quarter of the largest; their
+  node count over time shows whether they keep their mass (CG) or dissolve
+  into the other component (SC).
+* ``sc_mc_sigma(G_RB)``: surface tension of the two-component Shan-Chen model
+  from a Laplace test, dP = 2 sigma / R (Eq. YoungLaplace), with the pressure
+  p = (rho_R + rho_B) / 3 + (G_RB / rho0_X^2) rho_R rho_B / 3 of the cross
+  force (Eq. doublebeltrepulsionforce2 on belt 1) and R from the rho^N = 0
+  crossings along x through the centre.
+* ``ligament(precision)``: the high-density-ratio capsule (96 x 96 x 384,
+  walls on x and y, outflow on z, R0 = 8, length 320, density ratio 1000,
+  viscosity ratio 50, sigma = 0.01); the end positions from the interface
+  crossings along z near the axis, the retraction speed of each end against
+  the capillary speed sqrt(sigma / (rho_R R0)) of the contraction section,
+  the droplet count and divergence.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import inputs
+
+RP_R0 = 12.0
+RP_SHAPE = (512, 128, 128)
+
+
+def rp_wavelength(seed: int = 3):
+    """Wavelength in [9 R0, 12 R0] made commensurate with the 512-node axis,
+    and a phase, from the seed."""
+    rng = np.random.default_rng(seed)
+    lam = 512 / round(512 / rng.uniform(9 * RP_R0, 12 * RP_R0))
+    return lam, float(rng.uniform(0, 2 * math.pi))
+
+
+# Two-component Shan-Chen at density ratio 1: coupling SC_G, total density
+# SC_TOTAL per node; each phase holds its majority species at a and the other
+# species dissolved at b, the coexisting pair of the cross force with psi =
+# rho (equal chemical potentials ln rho_s + G rho_s' of both species in both
+# phases, which by symmetry leaves ln(a / b) = G (a - b), a + b = SC_TOTAL).
+# The 50/50 mixture is unstable to demixing since G_RB SC_TOTAL / 2 > 1.
+SC_G, SC_TOTAL = 1.5, 2.0
+
+
+def sc_mc_coexistence(G: float = SC_G, total: float = SC_TOTAL):
+    """(majority, minority) densities of the demixed phases."""
+    from scipy.optimize import brentq
+    h = total / 2.0
+    g = lambda d: math.log((h + d) / (h - d)) - G * 2.0 * d
+    if G * h <= 1.0:
+        raise ValueError("the mixture does not demix: G_RB * total / 2 <= 1")
+    d = brentq(g, 1e-9 * h, h * (1 - 1e-12))
+    return h + d, h - d
+
+
+SC_RHO, SC_MINOR = sc_mc_coexistence()
+
+
+def rp_params(M, model: str, sigma: float = 0.03):
+    nz, ny, nx = RP_SHAPE
+    if model == "CG":
+        p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=nx, ny=ny, nz=nz)
+        return M.params_from_sigma(p, sigma)
+    return M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=M.FP32, nx=nx, ny=ny, nz=nz,
+                         G_RB=SC_G, rho0_R=SC_RHO, rho0_B=SC_RHO)
+
+
+def rp_fields(model: str, seed: int = 3):
+    lam, phase = rp_wavelength(seed)
+    if model == "CG":
+        rR, rB = inputs.jet(RP_SHAPE, RP_R0, lam, 0.1, phase)
+    else:
+        rR, rB = inputs.jet(RP_SHAPE, RP_R0, lam, 0.1, phase, SC_RHO - SC_MINOR, SC_RHO - SC_MINOR)
+        rR, rB = rR + SC_MINOR, rB + SC_MINOR
+    return rR, rB, lam
+
+
+def rayleigh_plateau(M, model: str, steps: int = 30000, every: int = 500, seed: int = 3, sigma: float = 0.03,
+                     log=print):
+    """sigma: the colour-gradient surface tension (Eq. sigmaA); pass the
+    Shan-Chen one to compare the two at matched sigma."""
+    p = rp_params(M, model, sigma)
+    rR, rB, lam = rp_fields(model, seed)
+    s = M.Sim(p)
+    s.init_equilibrium(rR, rB)
+    history = []
+    t0 = time.perf_counter()
+    done = 0
+    status = M.OK
+    while done < steps:
+        st, k = s.step(min(every, steps - done), check_every=every)
+        done += k
+        n, sizes = s.droplets(64)
+        history.append((done, n, sizes[:16]))
+        if st != M.OK:
+            status = st
+            break
+    wall = time.perf_counter() - t0
+    s.close()
+    breakup = next((t for t, n, _ in history if n > 1), None)
+    sat = []
+    for t, n, sizes in history:
+        if n > 1:
+            big = sizes[0]
+            sat.append((t, sum(v for v in sizes if v < 0.25 * big), sum(1 for v in sizes if v < 0.25 * big),
+                        sum(1 for v in sizes if v >= 0.25 * big)))
+    out = dict(model=model, wavelength=lam, wavelengths_in_box=round(512 / lam), steps=done,
+               diverged=status != M.OK, breakup_step=breakup, wall_s=round(wall, 1),
+               glups=round(done * 512 * 128 * 128 / wall / 1e9, 2),
+               final_count=history[-1][1], final_sizes=history[-1][2],
+               satellites=[dict(step=t, nodes=m, count=c, main=mc) for t, m, c, mc in sat])
+    log(f"[rp] {model}: breakup at step {breakup}, final {history[-1][1]} droplets {history[-1][2][:8]}")
+    return out
+
+
+def sc_mc_sigma(M, G_RB: float = SC_G, R: float = 16.0, L: int = 64, steps: int = 8000):
+    """Laplace-test surface tension of the two-component Shan-Chen model."""
+    p = M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=M.FP32, nx=L, ny=L, nz=L, G_RB=G_RB,
+                      rho0_R=SC_RHO, rho0_B=SC_RHO)
+    rR, rB = inputs.droplet((L, L, L), R, SC_RHO - SC_MINOR, SC_RHO - SC_MINOR)
+    s = M.Sim(p)
+    s.init_equilibrium(rR + SC_MINOR, rB + SC_MINOR)
+    st, _ = s.step(steps, check_every=steps)
+    c = L // 2
+    xs, n = s.interface_crossings(0, c, c)
+    mR, mB, _ = s.moments()
+    mR, mB = mR.cpu().numpy(), mB.cpu().numpy()
+    s.close()
+    xpref = G_RB / p["rho0_X"] ** 2
+    pres = lambda a, b: (a + b) / 3.0 + xpref * a * b / 3.0
+    inside = (slice(c - 1, c + 1),) * 3
+    p_in = float(np.mean(pres(mR[inside], mB[inside])))
+    p_out = float(pres(mR[0, 0, 0], mB[0, 0, 0]))
+    radius = (xs[-1] - xs[0]) / 2.0 if n >= 2 else float("nan")
+    return dict(G_RB=G_RB, sigma=(p_in - p_out) * radius / 2.0, radius=radius, dP=p_in - p_out,
+                rho_in=(float(np.mean(mR[inside])), float(np.mean(mB[inside]))),
+                rho_out=(float(mR[0, 0, 0]), float(mB[0, 0, 0])), status_ok=st == M.OK)
+
+
+LIG_SHAPE = (384, 96, 96)
+
+
+def ligament(M, precision, steps: int = 40000, every: int = 2000, log=print):
+    nz, ny, nx = LIG_SHAPE
+    R0, length, sigma = 8.0, 320.0, 0.01
+    rR, rB = inputs.ligament(LIG_SHAPE, R0, length, 1000.0, 1.0, axis=2)
+    p = M.make_params(lattice=M.D3Q19, precision=precision, nx=nx, ny=ny, nz=nz, bc=(1, 1, 2),
+                      rho0_R=1000.0, rho0_B=1.0, tau_R=3.0, tau_B=0.55)
+    p = M.params_from_sigma(p, sigma)
+    s = M.Sim(p)
+    s.init_equilibrium(rR, rB)
+    cx, cy = nx // 2, ny // 2
+    ends = []
+    status = M.OK
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        xs, n = s.interface_crossings(2, cx, cy)
+        ends.append((done, xs[0] if n else float("nan"), xs[-1] if n else float("nan"), n))
+        if done >= steps:
+            break
+        st, k = s.step(min(every, steps - done), check_every=every)
+        done += k
+        if st != M.OK:
+            status = st
+            xs, n = s.interface_crossings(2, cx, cy)
+            ends.append((done, xs[0] if n else float("nan"), xs[-1] if n else float("nan"), n))
+            break
+    wall = time.perf_counter() - t0
+    count, sizes = s.droplets(16)
+    obs = s.observables()
+    s.close()
+    t = np.array([e[0] for e in ends], float)
+    lo = np.array([e[1] for e in ends])
+    hi = np.array([e[2] for e in ends])
+    # retraction speed of each end over the second half of the run
+    sel = t >= t[-1] / 2
+    v_lo = float(np.polyfit(t[sel], lo[sel], 1)[0]) if sel.sum() >= 2 else float("nan")
+    v_hi = float(-np.polyfit(t[sel], hi[sel], 1)[0]) if sel.sum() >= 2 else float("nan")
+    u_cap = math.sqrt(sigma / (1000.0 * R0))
+    out = dict(precision=precision, steps=done, diverged=status != M.OK or bool(obs["diverged"]),
+               length=[round(h - l, 2) for l, h in zip(lo, hi)], steps_sampled=[int(x) for x in t],
+               end_speed=(v_lo, v_hi), capillary_speed=u_cap, speed_ratio=((v_lo + v_hi) / 2) / u_cap,
+               final_count=count, final_sizes=sizes[:4], wall_s=round(wall, 1),
+               mass_R=obs["mass_R"], mass_B=obs["mass_B"])
+    log(f"[ligament] precision {precision}: {done} steps, length {out['length'][0]} -> {out['length'][-1]}, "
+        f"end speed {out['speed_ratio']:.2f} x sqrt(sigma/(rho_R R0)), {count} droplet(s)")
+    return out

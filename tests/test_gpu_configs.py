@@ -377,3 +377,30 @@ def test_droplet_collision_repulsion(M):
     assert out[(0.0, 0.06)][0] == 1
     assert out[(1.05e-2, 0.06)][0] == 2 and out[(1.05e-2, 0.06)][1] < 3.0
     assert out[(1.05e-2, 0.07)][0] == 1 and abs(out[(1.05e-2, 0.07)][1] - RD) < 0.05 * RD
+
+
+def test_rayleigh_plateau_satellites_cg_vs_sc():
+    """The breakup comparison at matched surface tension (128x128x512 jet,
+    R0 = 12, 5 wavelengths of 102.4, density ratio 1, FP32): the
+    two-component Shan-Chen sigma is measured by a Laplace test and the
+    colour-gradient A set to give the same sigma.  Both jets break into five
+    main drops; the colour-gradient satellites keep their volume, the
+    Shan-Chen ones dissolve into the other component within ~1000 steps of
+    breakup, the paper's finding for the two models."""
+    import paper_2110_05197_amd as M
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_05197_amd import studies
+    sc = studies.sc_mc_sigma(M)
+    say(f"[rp-satellites] Shan-Chen sigma {sc['sigma']:.4f}, R {sc['radius']:.2f}")
+    assert sc["status_ok"] and 0.05 < sc["sigma"] < 0.15
+    res = {m: studies.rayleigh_plateau(M, m, steps=6000, every=500, sigma=sc["sigma"], log=say)
+           for m in ("CG", "SC_MC")}
+    cg, scr = res["CG"], res["SC_MC"]
+    assert cg["breakup_step"] is not None and scr["breakup_step"] is not None
+    assert cg["final_count"] == 10 and cg["satellites"][-1]["count"] == 5
+    # satellite volume 1000 steps after pinch-off (settled) against the end
+    ref = next(s for s in cg["satellites"] if s["step"] >= cg["breakup_step"] + 1000)
+    assert abs(cg["satellites"][-1]["nodes"] - ref["nodes"]) < 0.05 * ref["nodes"]
+    assert scr["final_count"] == 5 and scr["satellites"][-1]["nodes"] == 0
