@@ -205,10 +205,10 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=100_000)
     ap.add_argument("--model", default="CG", choices=sorted(MODELS))
     ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
-    ap.add_argument("--study", choices=["rp", "ligament"],
+    ap.add_argument("--study", choices=["rp", "ligament", "oscillation"],
                     help="physics run of a paper case instead of the benchmark: the Rayleigh-Plateau jet "
-                         "(CG and SC, breakup and satellites) or the density-ratio-1000 ligament "
-                         "(mixed and FP16 storage)")
+                         "(CG and SC, breakup and satellites), the density-ratio-1000 ligament "
+                         "(mixed and FP16 storage) or the 128^3 oscillating droplet (FP32 and FP64)")
     ap.add_argument("--study-steps", type=int, default=None)
     args = ap.parse_args()
     if args.copy_probe:
@@ -228,6 +228,10 @@ def main():
             out = dict(study="rayleigh-plateau", sc_mc_sigma=sc,
                        runs=[studies.rayleigh_plateau(M, m, steps=steps, sigma=sc["sigma"], log=log)
                              for m in ("CG", "SC_MC")])
+        elif args.study == "oscillation":
+            steps = args.study_steps or 20000
+            out = dict(study="oscillation", runs=[studies.oscillation(M, prec, steps=steps, log=log)
+                                                  for prec in (M.FP32, M.FP64)])
         else:
             steps = args.study_steps or 40000
             out = dict(study="ligament", runs=[studies.ligament(M, prec, steps=steps, log=log)

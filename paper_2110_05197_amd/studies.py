@@ -198,3 +198,85 @@ def ligament(M, precision, steps: int = 40000, every: int = 2000, log=print):
     log(f"[ligament] precision {precision}: {done} steps, length {out['length'][0]} -> {out['length'][-1]}, "
         f"end speed {out['speed_ratio']:.2f} x sqrt(sigma/(rho_R R0)), {count} droplet(s)")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Oscillating droplet (the droplet-oscillation section; l = 2 shape mode)
+# ---------------------------------------------------------------------------
+def lamb_omega(sigma: float, R: float, rho_in: float = 1.0, rho_out: float = 1.0) -> float:
+    """Inviscid l = 2 frequency of a drop in a host fluid."""
+    return math.sqrt(24.0 * sigma / (R ** 3 * (3.0 * rho_in + 2.0 * rho_out)))
+
+
+def miller_scriven_omega(sigma, R, rho_in, rho_out, nu_in, nu_out):
+    """Lamb's frequency with the first viscous corrections of Miller and
+    Scriven (Eqs. millscriv-millscriv3)."""
+    den = 3.0 * rho_in + 2.0 * rho_out
+    w = lamb_omega(sigma, R, rho_in, rho_out)
+    a = (25.0 * math.sqrt(nu_in * nu_out) * rho_in * rho_out
+         / (math.sqrt(2.0) * R * den * (math.sqrt(nu_in) * rho_in + math.sqrt(nu_out) * rho_out)))
+    return w - 0.5 * a * math.sqrt(w) + 0.25 * a * a
+
+
+def fit_damped_cosine(t, r, w0):
+    """R(t) = R_D + b exp(-l t) cos(w t + ph) by least squares; (w, l, R_D)."""
+    from scipy.optimize import curve_fit
+    model = lambda t, a, b, lam, w, ph: a + b * np.exp(-lam * t) * np.cos(w * t + ph)
+    best = None
+    for ph0 in (0.0, math.pi / 2, math.pi, 3 * math.pi / 2):
+        try:
+            pp, _ = curve_fit(model, t, r, p0=[float(r.mean()), float(r[0] - r.mean()), 1e-4, w0, ph0],
+                              maxfev=20000)
+        except RuntimeError:
+            continue
+        res = float(np.sum((model(t, *pp) - r) ** 2))
+        if best is None or res < best[0]:
+            best = (res, pp)
+    if best is None:
+        return float("nan"), float("nan"), float("nan")
+    pp = best[1]
+    return abs(float(pp[3])), float(pp[2]), float(pp[0])
+
+
+def oscillation(M, precision, n: int = 128, steps: int = 20000, every: int = 20, seed: int = 2, log=print):
+    """Ellipsoid with semi-axes (24, 20, 20), each perturbed by U[-1, 1], tau
+    from U[0.55, 1.0], A = 0.005, density and viscosity ratio 1, n^3
+    periodic: the y-axis radius from the interface crossings every `every`
+    steps, its damped-cosine frequency against Lamb's and Miller-Scriven's."""
+    rng = np.random.default_rng(seed)
+    tau = float(rng.uniform(0.55, 1.0))
+    (rR, rB), axes = inputs.perturbed_ellipsoid((n, n, n), (24.0, 20.0, 20.0), seed=seed)
+    p = M.make_params(lattice=M.D3Q19, precision=precision, nx=n, ny=n, nz=n, A=0.005, tau_R=tau, tau_B=tau)
+    s = M.Sim(p)
+    s.init_equilibrium(rR, rB)
+    c = n // 2
+    t, r = [], []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        st, k = s.step(every, check_every=every)
+        done += k
+        xs, cnt = s.interface_crossings(1, c, c)
+        t.append(done)
+        r.append((xs[-1] - xs[0]) / 2.0 if cnt >= 2 else float("nan"))
+        if st != M.OK:
+            break
+    wall = time.perf_counter() - t0
+    o = s.observables()
+    s.close()
+    t, r = np.array(t, float), np.array(r)
+    sigma = M.sigma_from_params(p)
+    RD = (3.0 * o["red_volume"] / (4.0 * math.pi)) ** (1.0 / 3.0)
+    nu = (tau - 0.5) / 3.0
+    wL = lamb_omega(sigma, RD)
+    wMS = miller_scriven_omega(sigma, RD, 1.0, 1.0, nu, nu)
+    ok = np.isfinite(r)
+    w, lam, rfit = fit_damped_cosine(t[ok], r[ok], wMS)
+    out = dict(precision=precision, tau=tau, axes=[float(a) for a in axes], sigma=sigma, R_D=RD, steps=done,
+               omega=w, damping=lam, period=2 * math.pi / w if w == w and w > 0 else float("nan"),
+               omega_lamb=wL, omega_miller_scriven=wMS, err_vs_lamb=(w - wL) / wL, err_vs_ms=(w - wMS) / wMS,
+               wall_s=round(wall, 1), radius_first=float(r[0]), radius_last=float(r[-1]))
+    log(f"[oscillation] precision {precision} tau={tau:.3f} R_D={RD:.2f}: period {out['period']:.0f} steps, "
+        f"omega {w:.4e} vs Lamb {wL:.4e} ({out['err_vs_lamb']:+.1%}), Miller-Scriven {wMS:.4e} "
+        f"({out['err_vs_ms']:+.1%})")
+    return out
