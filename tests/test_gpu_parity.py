@@ -476,6 +476,49 @@ def test_batch_one_pass_bitwise(M):
             s.close()
 
 
+def test_batch_graph_replays_match_eager(M):
+    """The K-step graph of a batch (one-pass and two-pass groups, walls and
+    outflow, side-stream branches) replayed several times, with unrelated
+    eager device work and synchronisations between the replays, matches the
+    same batch stepped without a graph: equal step counts after every replay
+    and, at the end (members of a live batch cannot be read), equal
+    populations bit for bit; a wrong replay would leave its mark on the
+    final state."""
+    import torch
+    specs = [
+        dict(lattice=M.D3Q19, precision=M.FP32, nx=64, ny=16, nz=12, A=0.02),
+        dict(lattice=M.D3Q19, precision=M.FP32, nx=40, ny=12, nz=10, A=0.02, bc=(1, 0, 2)),
+        dict(lattice=M.D3Q19, precision=M.MIXED, nx=64, ny=8, nz=8, A=0.02, rho0_B=0.05),
+        dict(lattice=M.D2Q9, precision=M.FP64, nx=48, ny=40, nz=1, A=0.02, bc=(0, 1, 0)),
+    ]
+    def make():
+        sims = []
+        for i, kw in enumerate(specs):
+            p = M.make_params(**kw)
+            shape = (p["nz"], p["ny"], p["nx"])
+            rR, rB, u = cg_droplet_case(shape, 70 + i, gamma=p["rho0_R"] / p["rho0_B"], lattice=p["lattice"])
+            s = M.Sim(p)
+            s.init_equilibrium(rR, rB, u)
+            sims.append(s)
+        return sims
+    ga, eb = make(), make()
+    A = M.Batch(ga, [10 ** 6] * len(ga))
+    B = M.Batch(eb, [10 ** 6] * len(eb))
+    scratch = torch.randn(1 << 20, device="cuda")
+    for it in range(4):
+        A.step(9, use_graph=True)
+        B.step(9, use_graph=False)
+        scratch = torch.sin(scratch) * 1.0001      # unrelated eager work between replays
+        torch.cuda.synchronize()
+        sa, na = A.status()
+        sb, nb = B.status()
+        assert sa == sb == [M.RUNNING] * len(specs) and na == nb == [9 * (it + 1)] * len(specs)
+    A.close()
+    B.close()
+    for i, (a, b) in enumerate(zip(ga, eb)):
+        assert np.array_equal(a.export_f().cpu().numpy(), b.export_f().cpu().numpy()), i
+
+
 def test_batch_stops_diverged_member(M):
     p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=16, ny=16, nz=16, A=0.02)
     shape = (16, 16, 16)
