@@ -182,7 +182,8 @@ def test_cg_d2q9_walls(M, orc, kernel):
 # Shan-Chen variants and the repulsion force
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("lattice,prec,kernel,tol", [(1, 0, 1, 1e-10), (1, 1, 1, 2e-5), (1, 1, 2, 2e-5),
-                                                     (0, 0, 1, 1e-10)])
+                                                     (1, 0, 2, 1e-10), (0, 0, 1, 1e-10), (0, 0, 2, 1e-10),
+                                                     (0, 1, 2, 2e-5)])
 def test_sc_multiphase(M, orc, lattice, prec, kernel, tol):
     shape = (16, 16, 32) if lattice == 1 else (1, 40, 48)
     p = M.make_params(lattice=lattice, model=M.SC_MP, precision=prec, nx=shape[2], ny=shape[1],
@@ -192,7 +193,8 @@ def test_sc_multiphase(M, orc, lattice, prec, kernel, tol):
     compare(M, orc, p, rho, None, None, 100, tol, kernel=kernel, label="sc-mp")
 
 
-@pytest.mark.parametrize("lattice,prec,kernel,tol", [(1, 0, 1, 1e-10), (1, 1, 2, 2e-5), (0, 0, 1, 1e-10)])
+@pytest.mark.parametrize("lattice,prec,kernel,tol", [(1, 0, 1, 1e-10), (1, 1, 2, 2e-5), (1, 0, 2, 1e-10),
+                                                     (0, 0, 1, 1e-10), (0, 0, 2, 1e-10), (0, 1, 2, 2e-5)])
 def test_sc_two_component(M, orc, lattice, prec, kernel, tol):
     shape = (16, 16, 32) if lattice == 1 else (1, 40, 48)
     p = M.make_params(lattice=lattice, model=M.SC_MC, precision=prec, nx=shape[2], ny=shape[1],
