@@ -159,7 +159,7 @@ def test_mixed_beats_fp32_at_density_ratio_1000(M, orc):
 # --------------------------------------------------------------------------
 # Boundaries (walls on x/y, outflow on z)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("prec,kernel,tol", [(0, 1, 1e-10), (1, 1, 2e-5), (1, 2, 2e-5)])
+@pytest.mark.parametrize("prec,kernel,tol", [(0, 1, 1e-10), (0, 2, 1e-10), (1, 1, 2e-5), (1, 2, 2e-5)])
 def test_cg_walls_outflow(M, orc, prec, kernel, tol):
     shape = (40, 16, 32)
     p = M.make_params(lattice=M.D3Q19, precision=prec, nx=32, ny=16, nz=40, bc=(1, 1, 2),
