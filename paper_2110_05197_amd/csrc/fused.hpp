@@ -1,16 +1,17 @@
-// fused.hpp -- one-pass D3Q19 step: each block owns a TX x TY column of
-// nodes and marches it through a chunk of TZ planes.  The stencil inputs
-// (colour-gradient densities / pseudopotential) of a plane are computed from
-// its populations as they are loaded (two planes ahead of the collision),
-// for the tile and a one-node x-y halo ring, into a four-plane LDS ring; a
-// tile node's populations wait one iteration in the thread's LDS slot and are
-// collided from registers.  Only the halo ring's populations are read twice
-// (by this block and its neighbour, mostly from L2), so HBM traffic stays
-// near one read and one write of every population per step; no density field
-// is written.
+// fused.hpp -- one-pass step: each block owns a TX x TY column of nodes and
+// marches it through a chunk of TZ planes (D3Q19), or a row of TX nodes
+// through a chunk of rows (D2Q9, the box seen as nx x 1 x ny).  The stencil
+// inputs (colour-gradient densities / pseudopotential) of a plane are
+// computed from its populations as they are loaded (two planes ahead of the
+// collision), for the tile and a one-node halo ring, into a four-plane LDS
+// ring; a tile node's populations wait one iteration in the thread's LDS slot
+// and are collided from registers.  Only the halo ring's populations are read
+// twice (by this block and by its neighbour), so HBM traffic stays near one
+// read and one write of every population per step; no density field is
+// written.  The solo and the batched kernels share the column body.
 //
-// Requires nx % TX == 0 and ny % TY == 0 (the host falls back to the
-// two-pass kernels otherwise); any nz.
+// ny % TY == 0; any nx (the last column in x is masked when TX does not
+// divide it) and any nz.
 #pragma once
 
 #include <hip/hip_runtime.h>
