@@ -205,7 +205,15 @@ mclbm_status mclbm_init_equilibrium(mclbm_sim *sim, const double *d_rhoR, const 
 /* Advance nsteps time steps.  check_every > 0: every check_every steps (and
  * at the end) read the device divergence flag (synchronises) and stop early
  * with MCLBM_DIVERGED if it is set; check_every == 0: fully asynchronous, no
- * early exit.  *steps_done (may be NULL) receives the steps taken. */
+ * early exit.  *steps_done (may be NULL) receives the steps taken.
+ * With check_every == 0 the call only enqueues kernel launches on the sim's
+ * stream (no copy, fill or synchronisation), so a caller may capture it into
+ * a HIP graph.  The ping-pong buffer index and the step counter advance on
+ * the host when the launches are enqueued: a graph replayed more than once
+ * must hold an even number of steps (so each replay starts from the buffer
+ * the previous one wrote), and the counter counts the captured steps, not
+ * the replays.  Step once eagerly before capturing: the first launch of a
+ * kernel configuration in a process raises its dynamic-LDS limit. */
 mclbm_status mclbm_step(mclbm_sim *sim, int64_t nsteps, int64_t check_every, int64_t *steps_done);
 
 /* Per-node moments into device FP64 arrays (any may be NULL): rho_R, rho_B
