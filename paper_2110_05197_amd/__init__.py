@@ -214,7 +214,11 @@ def _dptr(t):
 
 
 class Sim:
-    """One simulation on caller (torch) memory; mirrors the mclbm_* calls."""
+    """One simulation on caller (torch) memory; mirrors the mclbm_* calls.
+
+    The library enqueues on `stream` (default: the current stream at
+    creation).  Tensors passed in or returned are ordered with the caller's
+    current stream at the time of the call, whichever stream that is."""
 
     def __init__(self, params: dict, device="cuda", stream=None):
         torch = _torch()
@@ -249,6 +253,23 @@ class Sim:
         except Exception:
             pass
 
+    def _after_caller(self):
+        """Order the sim's stream after the caller's current stream: the
+        library is about to read tensors the caller's stream produced, or to
+        write fresh tensors whose memory that stream last used."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _before_caller(self):
+        """Order the caller's current stream after the sim's stream: tensors
+        the library wrote on its stream are then safe to use on the caller's."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def _dev64(self, a, shape):
         torch = _torch()
         if a is None:
@@ -261,6 +282,7 @@ class Sim:
         tR = self._dev64(rhoR, self.shape)
         tB = self._dev64(rhoB, self.shape)
         tu = self._dev64(u, (3,) + self.shape)
+        self._after_caller()
         _check(lib().mclbm_init_equilibrium(self._h, _dptr(tR), _dptr(tB), _dptr(tu)),
                "mclbm_init_equilibrium")
         self._keep = (tR, tB, tu)   # alive until the stream has consumed them
@@ -279,7 +301,9 @@ class Sim:
         rR = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         rB = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._after_caller()
         _check(lib().mclbm_moments(self._h, _dptr(rR), _dptr(rB), _dptr(u)), "mclbm_moments")
+        self._before_caller()
         return rR, rB, u
 
     def observables(self) -> dict:
@@ -293,11 +317,14 @@ class Sim:
     def export_f(self):
         torch = _torch()
         f = torch.empty((self.ncomp, self.Q) + self.shape, dtype=torch.float64, device=self.device)
+        self._after_caller()
         _check(lib().mclbm_export_f(self._h, _dptr(f)), "mclbm_export_f")
+        self._before_caller()
         return f
 
     def import_f(self, f):
         t = self._dev64(f, (self.ncomp, self.Q) + self.shape)
+        self._after_caller()
         _check(lib().mclbm_import_f(self._h, _dptr(t)), "mclbm_import_f")
         self.stream.synchronize()
 
@@ -307,11 +334,15 @@ class Sim:
         _check(lib().mclbm_checkpoint_bytes(self._h, ctypes.byref(nb)), "mclbm_checkpoint_bytes")
         buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         step = ctypes.c_int64()
+        self._after_caller()
         _check(lib().mclbm_checkpoint(self._h, _dptr(buf), ctypes.byref(step)), "mclbm_checkpoint")
+        self._before_caller()
         return buf, step.value
 
     def restore(self, buf, step):
+        self._after_caller()
         _check(lib().mclbm_restore(self._h, _dptr(buf), int(step)), "mclbm_restore")
+        self._before_caller()   # buf may be freed or reused on the caller's stream
 
     def diverged(self) -> bool:
         d = ctypes.c_int32()

@@ -20,6 +20,21 @@ the equilibration each droplet gives
 and each series is fitted with E ∝ R^b and E_kin / A_d ∝ R^b, the fits the
 paper tabulates (Tables densErrors, viscErrors, radiusErrors).
 
+Study "ekin" (the stationary-droplet comparison of CG and SC, section
+3.1.2): droplets of R = 20 in a 96^3 periodic box, 10^5 steps,
+
+* Shan-Chen multiphase (psi = 1 - exp(-rho), FP64) over couplings G inside
+  the stable range the paper reports (4.2 < |G| < 6.5), each droplet started
+  at the flat-interface coexistence densities of its G; measured: rho_in and
+  rho_out at the droplet centre and the box corner, their ratio, sigma from
+  Young-Laplace with p = rho/3 + G psi^2/6 and the equimolar radius, and the
+  total kinetic energy E_kin;
+* colour gradient at sigma_th = 0.001 ... 0.3 for density ratios 1, 10,
+  100, 1000 (tau = 1 for both colours), E_kin at the end;
+
+and E_kin ∝ sigma^b fitted per series (the paper: b = 2 for CG at every
+density ratio, b = 3.3 for SC, whose density ratio stays below about 50).
+
 Readings: rho_B = 1 and rho_R = gamma (as for the other density-ratio cases);
 the viscosity ratio r is split as nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)
 with nu0 = 1/6, so that every tau stays in [0.55, 5.5]; the box is periodic,
@@ -86,32 +101,47 @@ def fit_slope(R, y):
     return float(np.polyfit(np.log(R[ok]), np.log(y[ok]), 1)[0])
 
 
-def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=print):
-    """Run one study as a batch; returns the per-case results and the fits."""
+def _batch_run(M, params, fields, steps, chunk, log, label):
+    """Advance one batch of droplets `steps` steps (K-step graphs of `chunk`),
+    printing progress about every 20 s; returns the sims, their status words
+    and step counts, and the wall time."""
     import torch
-    import paper_2110_05197_amd as M
-    todo = cases(study, radii)
     stream = torch.cuda.Stream()
-    sims, params = [], []
+    sims = []
     with torch.cuda.stream(stream):
-        for (R, g, r) in todo:
-            p = case_params(M, R, g, r)
-            L = p["nx"]
-            rR, rB = inputs.droplet((L, L, L), float(R), p["rho0_R"], p["rho0_B"])
+        for p, (rR, rB) in zip(params, fields):
             s = M.Sim(p, stream=stream)
             s.init_equilibrium(rR, rB)
             sims.append(s)
-            params.append(p)
     t0 = time.perf_counter()
     batch = M.Batch(sims, [steps] * len(sims), stream=stream)
-    done = 0
+    done, last = 0, t0
     while done < steps:
         k = min(chunk, steps - done)
         batch.step(k, use_graph=True)   # diverged droplets stop themselves
         done += k
+        if time.perf_counter() - last > 20.0:
+            stream.synchronize()
+            last = time.perf_counter()
+            log(f"[sweep] {label}: {done}/{steps} steps, {last - t0:.0f} s")
     st, counts = batch.status()
     batch.close()
-    wall = time.perf_counter() - t0
+    return sims, st, counts, time.perf_counter() - t0
+
+
+def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=print):
+    """Run one study as a batch; returns the per-case results and the fits."""
+    import paper_2110_05197_amd as M
+    if study == "ekin":
+        return run_ekin(steps=steps, chunk=chunk, log=log)
+    todo = cases(study, radii)
+    params, fields = [], []
+    for (R, g, r) in todo:
+        p = case_params(M, R, g, r)
+        L = p["nx"]
+        params.append(p)
+        fields.append(inputs.droplet((L, L, L), float(R), p["rho0_R"], p["rho0_B"]))
+    sims, st, counts, wall = _batch_run(M, params, fields, steps, chunk, log, study)
     results = []
     for (R, g, r), s, p, stat, n in zip(todo, sims, params, st, counts):
         o = s.observables()
@@ -130,3 +160,106 @@ def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=pri
     lups = sum(int(n) * p["nx"] ** 3 for p, n in zip(params, counts))
     log(f"[sweep] {study}: {len(todo)} droplets, {steps} steps, {wall:.1f} s, {lups / wall / 1e9:.2f} GLUPS")
     return dict(study=study, steps=steps, wall_s=wall, glups=lups / wall / 1e9, results=results, fits=fits)
+
+
+# --------------------------------------------------------------------------
+# Stationary droplet, CG against SC: spurious-current energy over sigma
+# --------------------------------------------------------------------------
+EKIN_R = 20
+EKIN_SIGMA = (0.001, 0.003, 0.01, 0.03, 0.1, 0.3)
+EKIN_GAMMA = (1, 10, 100, 1000)
+GSCAN = (-4.4, -4.7, -5.0, -5.3, -5.6, -5.9, -6.2)
+PRINTED_EKIN_B = {"CG": 2.0, "SC": 3.3}
+PRINTED_SC_MAX_RATIO = 50.0
+
+
+def cg_ekin_params(M, gamma, sigma, R=EKIN_R):
+    L = box_for(R)
+    prec = M.MIXED if gamma >= 100 else M.FP32
+    p = M.make_params(lattice=M.D3Q19, precision=prec, nx=L, ny=L, nz=L, rho0_R=float(gamma),
+                      rho0_B=1.0, tau_R=1.0, tau_B=1.0)
+    return M.params_from_sigma(p, sigma)
+
+
+def sc_ekin_params(M, G, R=EKIN_R):
+    """SC multiphase droplet at coupling G, reference densities at the
+    flat-interface coexistence pair of G."""
+    from .serve import sc_coexistence
+    L = box_for(R)
+    liq, gas = sc_coexistence(G)
+    return M.make_params(lattice=M.D3Q19, model=M.SC_MP, precision=M.FP64, nx=L, ny=L, nz=L, G=float(G),
+                         tau_R=1.0, rho0_R=liq, rho0_B=gas)
+
+
+def sc_pressure(rho, G):
+    """Equation of state of the SC multiphase model with psi = 1 - exp(-rho)
+    (rho_0 = 1) on a lattice with c_s^2 = 1/3: p = rho/3 + G psi^2 / 6."""
+    psi = 1.0 - math.exp(-rho)
+    return rho / 3.0 + G * psi * psi / 6.0
+
+
+def sc_measure(sim, p):
+    """rho_in (centre), rho_out (corner), ratio, sigma (Young-Laplace with
+    the equimolar radius) and E_kin of an equilibrated SC droplet."""
+    rho, _, _ = sim.moments()
+    L = p["nx"]
+    c = L // 2
+    r_in = float(rho[c, c, c])
+    r_out = float(rho[0, 0, 0])
+    o = sim.observables()
+    mass = o["mass_R"]
+    dr = r_in - r_out
+    R = (3.0 * (mass - r_out * L ** 3) / (4.0 * math.pi * dr)) ** (1.0 / 3.0) if dr > 0 else float("nan")
+    dP = sc_pressure(r_in, p["G"]) - sc_pressure(r_out, p["G"])
+    return dict(rho_in=r_in, rho_out=r_out, ratio=r_in / r_out if r_out > 0 else float("nan"), R=R,
+                sigma=dP * R / 2.0, ekin=o["ekin"], diverged=bool(o["diverged"]))
+
+
+def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=EKIN_GAMMA, couplings=GSCAN,
+             log=print):
+    """The CG and SC stationary droplets as one batch (three groups: CG FP32,
+    CG mixed, SC FP64); returns the per-case results and the E_kin fits."""
+    import paper_2110_05197_amd as M
+    todo, params, fields = [], [], []
+    L = box_for(EKIN_R)
+    for G in couplings:
+        p = sc_ekin_params(M, G)
+        rR, rB = inputs.droplet((L, L, L), float(EKIN_R), p["rho0_R"], p["rho0_B"])
+        todo.append(("SC", G))
+        params.append(p)
+        fields.append((rR + rB, None))
+    for g in gammas:
+        for sg in sigmas:
+            p = cg_ekin_params(M, g, sg)
+            todo.append(("CG", (g, sg)))
+            params.append(p)
+            fields.append(inputs.droplet((L, L, L), float(EKIN_R), p["rho0_R"], p["rho0_B"]))
+    sims, st, counts, wall = _batch_run(M, params, fields, steps, chunk, log, "ekin")
+    sc_rows, cg_rows = [], []
+    for (kind, key), s, p, stat, n in zip(todo, sims, params, st, counts):
+        bad = stat == M.STOPPED_DIVERGED
+        if kind == "SC":
+            m = sc_measure(s, p) if not bad else dict(diverged=True)
+            m.update(G=key, steps=int(n), diverged=bool(bad or m.get("diverged")))
+            sc_rows.append(m)
+        else:
+            o = s.observables()
+            m = dict(gamma=key[0], sigma=key[1], ekin=o["ekin"], steps=int(n),
+                     diverged=bool(bad or o["diverged"]))
+            if not m["diverged"]:
+                m["sigma_cal"] = measure(o, p)["sigma_cal"]
+            cg_rows.append(m)
+        s.close()
+    ok_sc = [m for m in sc_rows if not m["diverged"] and m["sigma"] > 0]
+    fits = {"SC": dict(b=fit_slope([m["sigma"] for m in ok_sc], [m["ekin"] for m in ok_sc]),
+                       b_printed=PRINTED_EKIN_B["SC"],
+                       max_ratio=max((m["ratio"] for m in ok_sc), default=float("nan")),
+                       max_ratio_printed=PRINTED_SC_MAX_RATIO)}
+    for g in gammas:
+        sel = [m for m in cg_rows if m["gamma"] == g and not m["diverged"]]
+        fits[f"CG gamma={g}"] = dict(b=fit_slope([m["sigma"] for m in sel], [m["ekin"] for m in sel]),
+                                     b_printed=PRINTED_EKIN_B["CG"], n=len(sel))
+    lups = sum(int(n) * p["nx"] ** 3 for p, n in zip(params, counts))
+    log(f"[sweep] ekin: {len(todo)} droplets, {steps} steps, {wall:.1f} s, {lups / wall / 1e9:.2f} GLUPS")
+    return dict(study="ekin", steps=steps, wall_s=wall, glups=lups / wall / 1e9, sc=sc_rows, cg=cg_rows,
+                fits=fits)

@@ -567,6 +567,35 @@ def test_solo_steps_captured_in_a_graph(M):
             b.close()
 
 
+def test_side_stream_sim_outputs_ordered_with_caller(M):
+    """A sim on a side stream with many steps still queued: moments, export
+    and checkpoint read from the caller's (default) stream right away equal
+    the same reads taken after the side stream has drained, and an import
+    from the default stream is seen by the side stream."""
+    import torch
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=128, ny=64, nz=64, A=0.02)
+    shape = (64, 64, 128)
+    rR, rB, u = cg_droplet_case(shape, 95)
+    s = torch.cuda.Stream()
+    a = M.Sim(p, stream=s)
+    a.init_equilibrium(rR, rB, u)
+    a.step(60)                                  # queued on the side stream
+    rho_now = a.moments()[0].cpu().numpy()      # default stream
+    f_now = a.export_f().cpu().numpy()
+    ck, n = a.checkpoint()
+    ck_now = ck.cpu().numpy()
+    s.synchronize()
+    with torch.cuda.stream(s):
+        rho_late = a.moments()[0].cpu().numpy()
+        f_late = a.export_f().cpu().numpy()
+    assert np.array_equal(rho_now, rho_late) and np.array_equal(f_now, f_late)
+    assert n == 60 and np.array_equal(ck_now, a.checkpoint()[0].cpu().numpy())
+    g = torch.from_numpy(f_late).cuda() * 1.0   # produced on the default stream
+    a.import_f(g)
+    assert np.array_equal(a.export_f().cpu().numpy(), f_late)
+    a.close()
+
+
 def test_batch_stops_diverged_member(M):
     p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=16, ny=16, nz=16, A=0.02)
     shape = (16, 16, 16)

@@ -90,6 +90,33 @@ def test_laplace_sweep_machinery(M):
     assert e1[12] < e1[8]
 
 
+def test_ekin_sweep_machinery(M):
+    """The CG-vs-SC stationary-droplet study (sweeps.run_ekin) on a reduced
+    case, R = 20 in 96^3, 4000 steps: SC at two couplings, CG at two sigmas
+    for density ratios 1 and 1000, one batch of three groups.  No
+    divergence; SC droplets keep densities near the flat coexistence pair of
+    their coupling, with a larger density ratio and a larger positive sigma
+    at the stronger coupling; CG spurious-current energy grows with sigma."""
+    from paper_2110_05197_amd import serve, sweeps
+    out = sweeps.run_ekin(steps=4000, chunk=500, sigmas=(0.01, 0.1), gammas=(1, 1000), couplings=(-4.8, -5.6),
+                          log=lambda *a: None)
+    sc, cg = out["sc"], out["cg"]
+    assert len(sc) == 2 and len(cg) == 4
+    assert not any(m["diverged"] for m in sc + cg)
+    for m in sc:
+        liq, gas = serve.sc_coexistence(m["G"])
+        assert abs(m["rho_in"] - liq) / liq < 0.1, m
+        assert 0.5 * gas < m["rho_out"] < 2.0 * gas, m
+        assert abs(m["R"] - sweeps.EKIN_R) < 2.0, m
+        assert m["sigma"] > 0, m
+    weak, strong = sc
+    assert strong["ratio"] > weak["ratio"] and strong["sigma"] > weak["sigma"]
+    for g in (1, 1000):
+        e = {m["sigma"]: m["ekin"] for m in cg if m["gamma"] == g}
+        assert e[0.1] > e[0.01] > 0, (g, e)
+    assert set(out["fits"]) == {"SC", "CG gamma=1", "CG gamma=1000"}
+
+
 def test_shortest_work_first_admission(M):
     """Policy "swf": with every request arrived and a node budget that holds
     only a few lattices, requests are admitted in order of the work they

@@ -54,3 +54,18 @@ def test_damped_cosine_fit_recovers_a_known_signal():
     r = 21.0 + 1.5 * np.exp(-2e-4 * t) * np.cos(7e-4 * t + 0.4)
     w, lam, rd = studies.fit_damped_cosine(t, r, 6e-4)
     assert abs(w - 7e-4) < 1e-8 and abs(lam - 2e-4) < 1e-8 and abs(rd - 21.0) < 1e-8
+
+
+def test_sc_pressure_equal_at_coexistence_and_flat_at_spinodals():
+    """The equation of state the E_kin study uses for Young-Laplace gives
+    equal pressures at the coexistence pair of the serving solver, and zero
+    slope at the spinodals 1 + G x (1 - x) = 0, x = exp(-rho)."""
+    from paper_2110_05197_amd import serve, sweeps
+    for G in (-4.4, -5.0, -5.9):
+        liq, gas = serve.sc_coexistence(G)
+        assert abs(sweeps.sc_pressure(liq, G) - sweeps.sc_pressure(gas, G)) < 1e-12
+        d = math.sqrt(1.0 + 4.0 / G)
+        for x in ((1 + d) / 2, (1 - d) / 2):
+            r, h = -math.log(x), 1e-6
+            slope = (sweeps.sc_pressure(r + h, G) - sweeps.sc_pressure(r - h, G)) / (2 * h)
+            assert abs(slope) < 1e-8
