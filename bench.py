@@ -200,7 +200,7 @@ def main():
                     help="only run a plain device copy of one step's population bytes (counter calibration)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only time the step's memory patterns without stencil or collision (ceilings)")
-    ap.add_argument("--sweep", choices=["density", "viscosity", "ekin"],
+    ap.add_argument("--sweep", choices=["density", "viscosity", "ekin", "ekin-tau"],
                     help="only run a static-droplet study of the paper (Laplace error, or CG vs SC "
                          "spurious-current energy over sigma) as one GPU batch")
     ap.add_argument("--sweep-steps", type=int, default=100_000)

@@ -34,6 +34,9 @@ Study "ekin" (the stationary-droplet comparison of CG and SC, section
 
 and E_kin ∝ sigma^b fitted per series (the paper: b = 2 for CG at every
 density ratio, b = 3.3 for SC, whose density ratio stays below about 50).
+Study "ekin-tau": the CG droplets at density ratio 1 with tau_R = 0.55,
+0.625, 0.75, 0.875, 1 and tau_B = 1 (the viscosity variant of the same
+comparison).
 
 Readings: rho_B = 1 and rho_R = gamma (as for the other density-ratio cases);
 the viscosity ratio r is split as nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)
@@ -134,6 +137,8 @@ def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=pri
     import paper_2110_05197_amd as M
     if study == "ekin":
         return run_ekin(steps=steps, chunk=chunk, log=log)
+    if study == "ekin-tau":
+        return run_ekin(steps=steps, chunk=chunk, gammas=(1,), taus=EKIN_TAU_R, couplings=(), log=log)
     todo = cases(study, radii)
     params, fields = [], []
     for (R, g, r) in todo:
@@ -169,15 +174,16 @@ EKIN_R = 20
 EKIN_SIGMA = (0.001, 0.003, 0.01, 0.03, 0.1, 0.3)
 EKIN_GAMMA = (1, 10, 100, 1000)
 GSCAN = (-4.4, -4.7, -5.0, -5.3, -5.6, -5.9, -6.2)
+EKIN_TAU_R = (0.55, 0.625, 0.75, 0.875, 1.0)
 PRINTED_EKIN_B = {"CG": 2.0, "SC": 3.3}
 PRINTED_SC_MAX_RATIO = 50.0
 
 
-def cg_ekin_params(M, gamma, sigma, R=EKIN_R):
+def cg_ekin_params(M, gamma, sigma, R=EKIN_R, tau_R=1.0):
     L = box_for(R)
     prec = M.MIXED if gamma >= 100 else M.FP32
     p = M.make_params(lattice=M.D3Q19, precision=prec, nx=L, ny=L, nz=L, rho0_R=float(gamma),
-                      rho0_B=1.0, tau_R=1.0, tau_B=1.0)
+                      rho0_B=1.0, tau_R=float(tau_R), tau_B=1.0)
     return M.params_from_sigma(p, sigma)
 
 
@@ -216,9 +222,11 @@ def sc_measure(sim, p):
 
 
 def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=EKIN_GAMMA, couplings=GSCAN,
-             log=print):
+             taus=(1.0,), log=print):
     """The CG and SC stationary droplets as one batch (three groups: CG FP32,
-    CG mixed, SC FP64); returns the per-case results and the E_kin fits."""
+    CG mixed, SC FP64); returns the per-case results and the E_kin fits.
+    `taus` lists red relaxation times for the CG droplets (tau_B = 1); with
+    more than one, each (density ratio, tau_R) series gets its own fit."""
     import paper_2110_05197_amd as M
     todo, params, fields = [], [], []
     L = box_for(EKIN_R)
@@ -229,11 +237,12 @@ def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=E
         params.append(p)
         fields.append((rR + rB, None))
     for g in gammas:
-        for sg in sigmas:
-            p = cg_ekin_params(M, g, sg)
-            todo.append(("CG", (g, sg)))
-            params.append(p)
-            fields.append(inputs.droplet((L, L, L), float(EKIN_R), p["rho0_R"], p["rho0_B"]))
+        for t in taus:
+            for sg in sigmas:
+                p = cg_ekin_params(M, g, sg, tau_R=t)
+                todo.append(("CG", (g, t, sg)))
+                params.append(p)
+                fields.append(inputs.droplet((L, L, L), float(EKIN_R), p["rho0_R"], p["rho0_B"]))
     sims, st, counts, wall = _batch_run(M, params, fields, steps, chunk, log, "ekin")
     sc_rows, cg_rows = [], []
     for (kind, key), s, p, stat, n in zip(todo, sims, params, st, counts):
@@ -244,7 +253,7 @@ def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=E
             sc_rows.append(m)
         else:
             o = s.observables()
-            m = dict(gamma=key[0], sigma=key[1], ekin=o["ekin"], steps=int(n),
+            m = dict(gamma=key[0], tau_R=key[1], sigma=key[2], ekin=o["ekin"], steps=int(n),
                      diverged=bool(bad or o["diverged"]))
             if not m["diverged"]:
                 m["sigma_cal"] = measure(o, p)["sigma_cal"]
@@ -256,9 +265,11 @@ def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=E
                        max_ratio=max((m["ratio"] for m in ok_sc), default=float("nan")),
                        max_ratio_printed=PRINTED_SC_MAX_RATIO)}
     for g in gammas:
-        sel = [m for m in cg_rows if m["gamma"] == g and not m["diverged"]]
-        fits[f"CG gamma={g}"] = dict(b=fit_slope([m["sigma"] for m in sel], [m["ekin"] for m in sel]),
-                                     b_printed=PRINTED_EKIN_B["CG"], n=len(sel))
+        for t in taus:
+            sel = [m for m in cg_rows if m["gamma"] == g and m["tau_R"] == t and not m["diverged"]]
+            name = f"CG gamma={g}" if len(taus) == 1 else f"CG gamma={g} tau_R={t}"
+            fits[name] = dict(b=fit_slope([m["sigma"] for m in sel], [m["ekin"] for m in sel]),
+                              b_printed=PRINTED_EKIN_B["CG"], n=len(sel))
     lups = sum(int(n) * p["nx"] ** 3 for p, n in zip(params, counts))
     log(f"[sweep] ekin: {len(todo)} droplets, {steps} steps, {wall:.1f} s, {lups / wall / 1e9:.2f} GLUPS")
     return dict(study="ekin", steps=steps, wall_s=wall, glups=lups / wall / 1e9, sc=sc_rows, cg=cg_rows,
