@@ -30,7 +30,8 @@ Study "ekin" (the stationary-droplet comparison of CG and SC, section
   Young-Laplace with p = rho/3 + G psi^2/6 and the equimolar radius, and the
   total kinetic energy E_kin;
 * colour gradient at sigma_th = 0.001 ... 0.3 for density ratios 1, 10,
-  100, 1000 (tau = 1 for both colours), E_kin at the end;
+  100, 1000 (tau = 1 for both colours; FP32, FP64 from density ratio 100),
+  E_kin at the end;
 
 and E_kin ∝ sigma^b fitted per series (the paper: b = 2 for CG at every
 density ratio, b = 3.3 for SC, whose density ratio stays below about 50).
@@ -180,8 +181,12 @@ PRINTED_SC_MAX_RATIO = 50.0
 
 
 def cg_ekin_params(M, gamma, sigma, R=EKIN_R, tau_R=1.0):
+    """CG droplet of the E_kin study: FP32 below density ratio 100, FP64 from
+    100 on (FP32 storage of the heavy phase's interface populations leaves a
+    velocity noise whose energy, at density ratio 1000, exceeds the spurious
+    currents of the smaller sigmas and keeps growing with time)."""
     L = box_for(R)
-    prec = M.MIXED if gamma >= 100 else M.FP32
+    prec = M.FP64 if gamma >= 100 else M.FP32
     p = M.make_params(lattice=M.D3Q19, precision=prec, nx=L, ny=L, nz=L, rho0_R=float(gamma),
                       rho0_B=1.0, tau_R=float(tau_R), tau_B=1.0)
     return M.params_from_sigma(p, sigma)
@@ -224,7 +229,7 @@ def sc_measure(sim, p):
 def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=EKIN_GAMMA, couplings=GSCAN,
              taus=(1.0,), log=print):
     """The CG and SC stationary droplets as one batch (three groups: CG FP32,
-    CG mixed, SC FP64); returns the per-case results and the E_kin fits.
+    CG FP64, SC FP64); returns the per-case results and the E_kin fits.
     `taus` lists red relaxation times for the CG droplets (tau_B = 1); with
     more than one, each (density ratio, tau_R) series gets its own fit."""
     import paper_2110_05197_amd as M
