@@ -42,8 +42,8 @@ comparison).
 Readings: rho_B = 1 and rho_R = gamma (as for the other density-ratio cases);
 the viscosity ratio r is split as nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)
 with nu0 = 1/6, so that every tau stays in [0.55, 5.5]; the box is periodic,
-L = 4 R + 16 (multiple of 8), the droplet centred; mixed precision (FP64 sums
-and light-phase arithmetic) for density ratios >= 100, FP32 otherwise.
+L = 4 R + 16 (multiple of 8), the droplet centred; FP64 for density ratios
+>= 100, FP32 otherwise.
 """
 from __future__ import annotations
 
@@ -67,11 +67,15 @@ def box_for(R: int) -> int:
     return int(math.ceil((4 * R + 16) / 8.0) * 8)
 
 
-def case_params(M, R, gamma, nu_ratio):
+def case_params(M, R, gamma, nu_ratio, heavy=None):
+    """Laplace-study droplet; FP32 below density ratio 100, `heavy` (default
+    FP64) from 100 on: there the pressure jump is about 1e-3 of either
+    phase's pressure, so sigma_cal needs rho_in to about 1e-4, which FP32
+    storage of the heavy phase does not hold over 10^5 steps."""
     L = box_for(R)
     nu0 = 1.0 / 6.0
     nuR, nuB = nu0 * math.sqrt(nu_ratio), nu0 / math.sqrt(nu_ratio)
-    prec = M.MIXED if gamma >= 100 else M.FP32
+    prec = (M.FP64 if heavy is None else heavy) if gamma >= 100 else M.FP32
     p = M.make_params(lattice=M.D3Q19, precision=prec, nx=L, ny=L, nz=L, rho0_R=float(gamma),
                       rho0_B=1.0, tau_R=0.5 + 3 * nuR, tau_B=0.5 + 3 * nuB)
     return M.params_from_sigma(p, SIGMA)

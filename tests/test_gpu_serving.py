@@ -70,10 +70,11 @@ def test_served_result_equals_solo(M):
 
 def test_laplace_sweep_machinery(M):
     """The static-droplet sweep (sweeps.run) on a reduced case: R = 8, 12,
-    density ratios 1 and 1000 in one batch (FP32 and mixed groups), 20000
-    steps: no divergence, sigma_cal within 40 % of sigma_th, the measured
-    radius within 1 of the initial one, and the Laplace error smaller at
-    the larger radius for density ratio 1."""
+    density ratios 1 and 1000 in one batch (FP32 and FP64 groups), 20000
+    steps: no divergence, the measured radius within 1 of the initial one,
+    sigma_cal within 10 % of sigma_th at density ratio 1 and within 50 % at
+    1000 (whose interface is as wide as a fifth of these radii), and the
+    Laplace error smaller at the larger radius for both."""
     from paper_2110_05197_amd import sweeps
     orig = sweeps.cases
     try:
@@ -84,10 +85,11 @@ def test_laplace_sweep_machinery(M):
     res = out["results"]
     assert len(res) == 4 and not any(m["diverged"] for m in res)
     for m in res:
-        assert abs(m["sigma_cal"] - 0.01) < 0.004
+        assert abs(m["sigma_cal"] - 0.01) < (0.001 if m["gamma"] == 1 else 0.005), m
         assert abs(m["R"] - m["R0"]) < 1.0
-    e1 = {m["R0"]: m["E"] for m in res if m["gamma"] == 1}
-    assert e1[12] < e1[8]
+    for g in (1, 1000):
+        e = {m["R0"]: m["E"] for m in res if m["gamma"] == g}
+        assert e[12] < e[8], (g, e)
 
 
 def test_ekin_sweep_machinery(M):
