@@ -21,7 +21,7 @@ and each series is fitted with E ∝ R^b and E_kin / A_d ∝ R^b, the fits the
 paper tabulates (Tables densErrors, viscErrors, radiusErrors).
 
 Study "ekin" (the stationary-droplet comparison of CG and SC, section
-3.1.2): droplets of R = 20 in a 96^3 periodic box, 10^5 steps,
+3.1.2): droplets of R = 20 in the same 64^3 periodic box, 10^5 steps,
 
 * Shan-Chen multiphase (psi = 1 - exp(-rho), FP64) over couplings G inside
   the stable range the paper reports (4.2 < |G| < 6.5), each droplet started
@@ -42,8 +42,8 @@ comparison).
 Readings: rho_B = 1 and rho_R = gamma (as for the other density-ratio cases);
 the viscosity ratio r is split as nu_R = nu0 sqrt(r), nu_B = nu0 / sqrt(r)
 with nu0 = 1/6, so that every tau stays in [0.55, 5.5]; the box is periodic,
-L = 4 R + 16 (multiple of 8), the droplet centred; FP64 for density ratios
->= 100, FP32 otherwise.
+64^3 for every radius (the domain of the Laplace section), the droplet
+centred; FP64 for density ratios >= 100, FP32 otherwise.
 """
 from __future__ import annotations
 
@@ -63,8 +63,12 @@ RADII = (8, 12, 16, 20)
 SIGMA = 0.01
 
 
+LAPLACE_BOX = 64
+
+
 def box_for(R: int) -> int:
-    return int(math.ceil((4 * R + 16) / 8.0) * 8)
+    """Periodic cube of the Laplace section: 64^3 whatever the radius."""
+    return LAPLACE_BOX
 
 
 def case_params(M, R, gamma, nu_ratio, heavy=None):

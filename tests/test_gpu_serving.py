@@ -94,7 +94,7 @@ def test_laplace_sweep_machinery(M):
 
 def test_ekin_sweep_machinery(M):
     """The CG-vs-SC stationary-droplet study (sweeps.run_ekin) on a reduced
-    case, R = 20 in 96^3, 4000 steps: SC at two couplings, CG at two sigmas
+    case, R = 20 in 64^3, 4000 steps: SC at two couplings, CG at two sigmas
     for density ratios 1 and 1000, one batch of three groups.  No
     divergence; SC droplets keep densities near the flat coexistence pair of
     their coupling, with a larger density ratio and a larger positive sigma
