@@ -8,17 +8,21 @@ nu_R/nu_B = 1, 2, 5, 10, 100.  sigma_th = 0.01 throughout (Eq. sigmaA).  After
 the equilibration each droplet gives
 
 * sigma_cal from Young-Laplace in 3-D, dP = 2 sigma / R (Eq. YoungLaplace),
-  with p_k = rho_k (1 - alpha_k) / 2 (the sound speed of colour k on D3Q19,
-  Eq. gamma) from the epsilon-masked inside/outside densities and R the
-  equimolar radius of the red mass, (3 M_R / (4 pi rho_in))^(1/3) (reading:
-  the red volume sum (1 + rho^N)/2 puts the interface at rho^N = 0, which at a
-  density ratio lies far out on the light side);
+  with p_k = rho_k (1 - alpha_k) / 2 (Eq. CGpressure) from the
+  epsilon-masked inside/outside densities (Eqs. rhoin, rhoout) and R the
+  radius of the colour interface rho^N = 0, from the red volume
+  sum (1 + rho^N)/2 (reading: the paper does not say how it measures R; at a
+  density ratio this interface lies well out on the light side of the
+  equimolar radius of the red mass, 14.0 against 8.4 for R = 8 at density
+  ratio 1000, and only the interface radius gives the paper's finding that
+  the error falls as the density ratio grows);
 * the error E = |sigma_th - sigma_cal| / sigma_th;
 * the kinetic energy of the spurious currents per droplet area,
-  E_kin / (4 pi R^2);
+  E_kin / A_d with A_d = 4 pi R^2 at the set radius;
 
-and each series is fitted with E ∝ R^b and E_kin / A_d ∝ R^b, the fits the
-paper tabulates (Tables densErrors, viscErrors, radiusErrors).
+and each series is fitted against the set radii R = 8 ... 20 with E ∝ R^b and
+E_kin / A_d ∝ R^b, the fits the paper tabulates (Tables densErrors,
+viscErrors, radiusErrors).
 
 Study "ekin" (the stationary-droplet comparison of CG and SC, section
 3.1.2): droplets of R = 20 in the same 64^3 periodic box, 10^5 steps,
@@ -93,16 +97,18 @@ def cases(study: str, radii=RADII):
     raise ValueError(study)
 
 
-def measure(obs, p):
-    """sigma_cal, E and E_kin / A_d of one equilibrated droplet."""
+def measure(obs, p, R0=None):
+    """sigma_cal, E and E_kin / A_d of one equilibrated droplet (A_d at the
+    set radius R0 when given, else at the interface radius)."""
     aR = 1.0 - (1.0 - p["alpha_B"]) * p["rho0_B"] / p["rho0_R"]   # Eq. gamma
     cR2, cB2 = (1.0 - aR) / 2.0, (1.0 - p["alpha_B"]) / 2.0
-    R = (3.0 * obs["mass_R"] / (4.0 * math.pi * obs["rho_in"])) ** (1.0 / 3.0)
-    R_vol = (3.0 * obs["red_volume"] / (4.0 * math.pi)) ** (1.0 / 3.0)
+    R = (3.0 * obs["red_volume"] / (4.0 * math.pi)) ** (1.0 / 3.0)
+    R_eq = (3.0 * obs["mass_R"] / (4.0 * math.pi * obs["rho_in"])) ** (1.0 / 3.0)
     dP = obs["rho_in"] * cR2 - obs["rho_out"] * cB2
     sigma_cal = dP * R / 2.0
-    return dict(R=R, R_red_volume=R_vol, sigma_cal=sigma_cal, E=abs(SIGMA - sigma_cal) / SIGMA,
-                ekin_per_area=obs["ekin"] / (4.0 * math.pi * R * R), eps=obs["eps_used"])
+    Ra = R if R0 is None else R0
+    return dict(R=R, R_equimolar=R_eq, sigma_cal=sigma_cal, E=abs(SIGMA - sigma_cal) / SIGMA,
+                ekin_per_area=obs["ekin"] / (4.0 * math.pi * Ra * Ra), eps=obs["eps_used"])
 
 
 def fit_slope(R, y):
@@ -159,7 +165,7 @@ def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=pri
     results = []
     for (R, g, r), s, p, stat, n in zip(todo, sims, params, st, counts):
         o = s.observables()
-        m = measure(o, p)
+        m = measure(o, p, R0=R)
         m.update(R0=R, gamma=g, nu_ratio=r, steps=int(n), diverged=bool(o["diverged"] or stat == M.STOPPED_DIVERGED))
         results.append(m)
         s.close()
@@ -167,8 +173,8 @@ def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=pri
     fits = {}
     for v in sorted({m[key] for m in results}):
         sel = [m for m in results if m[key] == v and not m["diverged"]]
-        fits[v] = dict(b_E=fit_slope([m["R"] for m in sel], [m["E"] for m in sel]),
-                       b_ekin=fit_slope([m["R"] for m in sel], [m["ekin_per_area"] for m in sel]),
+        fits[v] = dict(b_E=fit_slope([m["R0"] for m in sel], [m["E"] for m in sel]),
+                       b_ekin=fit_slope([m["R0"] for m in sel], [m["ekin_per_area"] for m in sel]),
                        b_E_printed=PRINTED_B[study].get(v if study == "viscosity" else int(v)),
                        b_ekin_printed=PRINTED_B["ekin"].get(int(v)) if study == "density" else None)
     lups = sum(int(n) * p["nx"] ** 3 for p, n in zip(params, counts))
