@@ -17,6 +17,9 @@ reporting the quantities the paper measures on them.
   p = (rho_R + rho_B) / 3 + (G_RB / rho0_X^2) rho_R rho_B / 3 of the cross
   force (Eq. doublebeltrepulsionforce2 on belt 1) and R from the rho^N = 0
   crossings along x through the centre.
+* ``ligament_contraction()``: the capsules of Table contrParams (128 x 64 x
+  64 periodic, sets 1-4, plus set 1 without the enhanced equilibrium), the
+  endpoint speed after start-up against sqrt(sigma / (rho_R R0)).
 * ``ligament(precision)``: the high-density-ratio capsule (96 x 96 x 384,
   walls on x and y, outflow on z, R0 = 8, length 320, density ratio 1000,
   viscosity ratio 50, sigma = 0.01); the end positions from the interface
@@ -197,6 +200,103 @@ def ligament(M, precision, steps: int = 40000, every: int = 2000, log=print):
                mass_R=obs["mass_R"], mass_B=obs["mass_B"])
     log(f"[ligament] precision {precision}: {done} steps, length {out['length'][0]} -> {out['length'][-1]}, "
         f"end speed {out['speed_ratio']:.2f} x sqrt(sigma/(rho_R R0)), {count} droplet(s)")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Ligament contraction (Table contrParams, sets 1-4)
+# ---------------------------------------------------------------------------
+CONTR_SHAPE = (64, 64, 128)     # (nz, ny, nx): 128 x 64 x 64 periodic, axis along x
+CONTR_SETS = (
+    dict(name="1", model="CG", rho=(2.0, 0.1), tau=(1.0, 0.55), sigma=0.05, R0=12.0, L=112.0, enhanced=1),
+    dict(name="1 plain", model="CG", rho=(2.0, 0.1), tau=(1.0, 0.55), sigma=0.05, R0=12.0, L=112.0, enhanced=0),
+    dict(name="2", model="CG", rho=(1.99, 0.165), tau=(1.0, 1.0), sigma=0.078, R0=10.0, L=100.0, enhanced=1),
+    dict(name="3", model="SC", G=-5.0, tau=(1.0,), R0=10.0, L=100.0),
+    dict(name="2 matched", model="CG", match_sc=True, tau=(1.0, 1.0), R0=10.0, L=100.0, enhanced=1),
+    dict(name="4", model="CG", rho=(1.99, 0.165), tau=(1.0, 0.55), sigma=0.078, R0=10.0, L=100.0, enhanced=1),
+)
+
+
+def sc_mp_sigma(M, G: float, R: int = 16, steps: int = 20000):
+    """Surface tension and the drop/vapour densities of the SC multiphase model
+    at coupling G: a droplet of radius R in the 64^3 Laplace box, started at
+    the flat coexistence pair, Young-Laplace with p = rho/3 + G psi^2/6."""
+    from . import sweeps
+    p = sweeps.sc_ekin_params(M, G, R=R)
+    L = p["nx"]
+    rR, rB = inputs.droplet((L, L, L), float(R), p["rho0_R"], p["rho0_B"])
+    s = M.Sim(p)
+    s.init_equilibrium(rR + rB, None)
+    s.step(steps)
+    m = sweeps.sc_measure(s, p)
+    s.close()
+    return m
+
+
+def contraction_run(M, cfg: dict, span: float = 4.5, fit=(2.0, 4.0)):
+    """One ligament of Table contrParams (FP64): the capsule of radius R0 and
+    length L along x, its endpoint x_e(t) from the outermost interface
+    crossing on the axis, sampled about 30 times per capillary time
+    t_cap = sqrt(rho_R R0^3 / sigma) up to `span` t_cap; the endpoint speed is
+    the slope over t / t_cap in `fit`, divided by the Srivastava speed
+    sqrt(sigma / (rho_R R0)) of the contraction section."""
+    nz, ny, nx = CONTR_SHAPE
+    R0, length = cfg["R0"], cfg["L"]
+    if cfg["model"] == "SC":
+        m = sc_mp_sigma(M, cfg["G"])
+        rhoR, rhoB, sigma = m["rho_in"], m["rho_out"], m["sigma"]
+        p = M.make_params(lattice=M.D3Q19, model=M.SC_MP, precision=M.FP64, nx=nx, ny=ny, nz=nz,
+                          G=cfg["G"], tau_R=cfg["tau"][0], rho0_R=rhoR, rho0_B=rhoB)
+        rR, rB = inputs.ligament(CONTR_SHAPE, R0, length, rhoR, rhoB, axis=0)
+        fields = (rR + rB, None)
+    else:
+        if cfg.get("match_sc"):
+            m = sc_mp_sigma(M, -5.0)
+            rhoR, rhoB, sigma = m["rho_in"], m["rho_out"], m["sigma"]
+        else:
+            (rhoR, rhoB), sigma = cfg["rho"], cfg["sigma"]
+        p = M.make_params(lattice=M.D3Q19, precision=M.FP64, nx=nx, ny=ny, nz=nz, rho0_R=rhoR, rho0_B=rhoB,
+                          tau_R=cfg["tau"][0], tau_B=cfg["tau"][1], enhanced_eq=cfg["enhanced"])
+        p = M.params_from_sigma(p, sigma)
+        fields = inputs.ligament(CONTR_SHAPE, R0, length, rhoR, rhoB, axis=0)
+    tcap = math.sqrt(rhoR * R0 ** 3 / sigma)
+    u_an = math.sqrt(sigma / (rhoR * R0))
+    every = max(2, int(round(tcap / 30.0)))
+    s = M.Sim(p)
+    s.init_equilibrium(*fields)
+    ts, xe, status = [], [], M.OK
+    for k in range(int(span * tcap / every)):
+        st, _ = s.step(every, check_every=every)
+        if st != M.OK:
+            status = st
+            break
+        pos, n = s.interface_crossings(0, ny // 2, nz // 2)
+        if n < 2:
+            break
+        ts.append((k + 1) * every / tcap)
+        xe.append((pos[-1] - (nx - 1) / 2.0) / R0)
+    s.close()
+    ts, xe = np.array(ts), np.array(xe)
+    sel = (ts >= fit[0]) & (ts <= fit[1])
+    speed = -float(np.polyfit(ts[sel], xe[sel], 1)[0]) if sel.sum() >= 3 else float("nan")
+    mu = rhoR * (cfg["tau"][0] - 0.5) / 3.0
+    return dict(set=cfg["name"], model=cfg["model"], rho_R=rhoR, rho_B=rhoB, sigma=sigma, R0=R0, L=length,
+                tau=cfg["tau"], t_cap=tcap, u_analytic=u_an, speed_ratio=speed,
+                Oh=mu / math.sqrt(rhoR * sigma * length), diverged=status != M.OK,
+                t=[round(x, 3) for x in ts[::3]], x_end=[round(x, 4) for x in xe[::3]])
+
+
+def ligament_contraction(M, sets=CONTR_SETS, log=print):
+    """Every set of Table contrParams (plus set 1 without the enhanced
+    equilibrium, and set 2 re-run at the surface tension and densities the
+    SC model of set 3 actually has here, for a matched CG-SC pair)."""
+    out = []
+    for cfg in sets:
+        r = contraction_run(M, cfg)
+        log(f"[contraction] set {r['set']} ({r['model']}): sigma {r['sigma']:.4f}, rho {r['rho_R']:.3f}/"
+            f"{r['rho_B']:.3f}, Oh {r['Oh']:.3f}, t_cap {r['t_cap']:.1f}: endpoint speed "
+            f"{r['speed_ratio']:.3f} x sqrt(sigma/(rho_R R0))")
+        out.append(r)
     return out
 
 

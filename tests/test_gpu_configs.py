@@ -320,6 +320,29 @@ def test_ligament_contraction_enhanced_equilibrium(M):
     assert ratio[0] < 0.85 * ratio[1]
 
 
+def test_ligament_contraction_table_sets(M):
+    """Sets 2-4 of Table contrParams (studies.contraction_run, FP64): with
+    the ambient at tau_B = 0.55 (set 4) the endpoint retracts at the
+    Srivastava speed within 15 % (measured 0.90 of it); with tau_B = 1 (set 2)
+    it is slower (measured 0.78), as the paper finds; the Shan-Chen ligament
+    (set 3, G = -5, its own sigma 0.034 and densities from a Laplace run)
+    contracts at a speed within 25 % of the CG ligament matched to those
+    values (measured 0.88 and 0.76)."""
+    from paper_2110_05197_amd import studies
+    r = {}
+    for cfg in studies.CONTR_SETS:
+        if cfg["name"] in ("2", "3", "2 matched", "4"):
+            say(f"[contraction] set {cfg['name']}")
+            out = studies.contraction_run(M, cfg)
+            assert not out["diverged"], out
+            r[cfg["name"]] = out["speed_ratio"]
+            say(f"[contraction] set {cfg['name']}: {out['speed_ratio']:.3f}")
+    assert 0.85 < r["4"] < 1.1
+    assert r["2"] < r["4"] - 0.05
+    assert 0.7 < r["3"] < 1.05
+    assert abs(r["3"] - r["2 matched"]) < 0.25 * r["2 matched"]
+
+
 def test_rayleigh_plateau_criterion(M):
     """A periodic jet R0 = 12 with a 0.1 R0 sinusoidal perturbation of
     wavelength lambda (one wavelength per box, 64x64xlambda, CG, sigma via
