@@ -206,11 +206,12 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=100_000)
     ap.add_argument("--model", default="CG", choices=sorted(MODELS))
     ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
-    ap.add_argument("--study", choices=["rp", "ligament", "oscillation", "contraction"],
+    ap.add_argument("--study", choices=["rp", "ligament", "oscillation", "contraction", "dropOsc"],
                     help="physics run of a paper case instead of the benchmark: the Rayleigh-Plateau jet "
                          "(CG and SC, breakup and satellites), the density-ratio-1000 ligament "
                          "(mixed and FP16 storage), the 128^3 oscillating droplet (FP32 and FP64) or the "
-                         "ligament contraction sets of Table contrParams (CG and SC)")
+                         "ligament contraction sets of Table contrParams (CG and SC), or the droplet "
+                         "oscillations of Table dropOscParams at R_D = 12-49 (CG and SC)")
     ap.add_argument("--study-steps", type=int, default=None)
     args = ap.parse_args()
     if args.copy_probe:
@@ -230,6 +231,8 @@ def main():
             out = dict(study="rayleigh-plateau", sc_mc_sigma=sc,
                        runs=[studies.rayleigh_plateau(M, m, steps=steps, sigma=sc["sigma"], log=log)
                              for m in ("CG", "SC_MC")])
+        elif args.study == "dropOsc":
+            out = dict(study="droplet-oscillation", runs=studies.oscillation_table(M, log=log))
         elif args.study == "contraction":
             out = dict(study="ligament-contraction", runs=studies.ligament_contraction(M, log=log))
         elif args.study == "oscillation":

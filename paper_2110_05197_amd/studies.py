@@ -380,3 +380,103 @@ def oscillation(M, precision, n: int = 128, steps: int = 20000, every: int = 20,
         f"omega {w:.4e} vs Lamb {wL:.4e} ({out['err_vs_lamb']:+.1%}), Miller-Scriven {wMS:.4e} "
         f"({out['err_vs_ms']:+.1%})")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Oscillating droplet at the parameters of Table dropOscParams
+# ---------------------------------------------------------------------------
+OSC_RHO = (2.73, 0.073)
+OSC_SIGMA = 0.183
+OSC_RADII = (12, 25, 37, 49)
+PRINTED_DROPOSC = {   # Table dropOsc: (R_D, omega_2, E in %)
+    "CG": ((11.65, 14.65e-3, 11.51), (24.97, 5.20e-3, 2.49), (36.97, 2.97e-3, 0.31), (48.95, 1.96e-3, 0.16)),
+    "SC": ((11.79, 1.17e-3, 27.96), (24.62, 4.44e-3, 15.45), (37.02, 2.62e-3, 10.52), (48.60, 1.94e-3, 7.77)),
+}
+
+
+def osc_box(R: float):
+    """(nz, ny, nx): the 160 x 160 x 240 box of the oscillation section, long
+    axis along z; 240 x 240 x 360 from R_D = 49 on (the section enlarges the
+    box there to keep the droplet clear of its periodic images)."""
+    return (360, 240, 240) if R >= 45 else (240, 160, 160)
+
+
+def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float = 1.25, log=print):
+    """One droplet of Table dropOscParams (FP64, tau = 1 in both phases): a
+    prolate ellipsoid of volume (4/3) pi R^3 and axis ratio `aspect` along z,
+    its y-axis radius R(t) through the box centre from the interface crossings
+    (rho^N = 0 for CG, the mid density for SC) about 40 times per period, the
+    damped-cosine fit R(t) = R_D + b exp(-l t) cos(w t + ph), and the error of
+    w against Miller-Scriven (Eqs. millscriv-millscriv3) at the fitted R_D.
+
+    CG: rho 2.73 / 0.073, sigma 0.183.  SC (multiphase): the coupling whose
+    coexistence has the same density ratio (37.4), densities and sigma from a
+    Laplace run of that model (the paper's G = -6 maps to other densities in
+    its pseudopotential, R17)."""
+    from .serve import sc_coupling_for_ratio
+    shape = osc_box(R)
+    nz, ny, nx = shape
+    a = R / aspect ** (1.0 / 3.0)
+    axes = (a, a, a * aspect)
+    if model == "SC":
+        G = sc_coupling_for_ratio(OSC_RHO[0] / OSC_RHO[1])
+        m = sc_mp_sigma(M, G)
+        rho_in, rho_out, sigma = m["rho_in"], m["rho_out"], m["sigma"]
+        p = M.make_params(lattice=M.D3Q19, model=M.SC_MP, precision=M.FP64, nx=nx, ny=ny, nz=nz, G=G,
+                          tau_R=1.0, rho0_R=rho_in, rho0_B=rho_out)
+        rR, rB = inputs.ellipsoid(shape, axes, rho_in, rho_out)
+        fields = (rR + rB, None)
+    else:
+        G = None
+        (rho_in, rho_out), sigma = OSC_RHO, OSC_SIGMA
+        p = M.make_params(lattice=M.D3Q19, precision=M.FP64, nx=nx, ny=ny, nz=nz, rho0_R=rho_in,
+                          rho0_B=rho_out, tau_R=1.0, tau_B=1.0)
+        p = M.params_from_sigma(p, sigma)
+        fields = inputs.ellipsoid(shape, axes, rho_in, rho_out)
+    nu = 1.0 / 6.0
+    w_guess = miller_scriven_omega(sigma, R, rho_in, rho_out, nu, nu)
+    period = 2.0 * math.pi / w_guess
+    every = max(2, int(round(period / 40.0)))
+    steps = int(periods * period)
+    s = M.Sim(p)
+    s.init_equilibrium(*fields)
+    t, r, status = [], [], M.OK
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        st, k = s.step(every, check_every=every)
+        done += k
+        if st != M.OK:
+            status = st
+            break
+        xs, cnt = s.interface_crossings(1, nx // 2, nz // 2)
+        t.append(done)
+        r.append((xs[-1] - xs[0]) / 2.0 if cnt >= 2 else float("nan"))
+    wall = time.perf_counter() - t0
+    s.close()
+    t, r = np.array(t, float), np.array(r)
+    ok = np.isfinite(r) & (t >= 0.25 * period)      # leave out the interface's first settling
+    if ok.sum() >= 20:
+        w, lam, RD = fit_damped_cosine(t[ok], r[ok], w_guess)
+    else:
+        w = lam = RD = float("nan")
+    w_ms = miller_scriven_omega(sigma, RD, rho_in, rho_out, nu, nu) if RD == RD else float("nan")
+    out = dict(model=model, R=R, box=[nx, ny, nz], G=G, rho_in=rho_in, rho_out=rho_out, sigma=sigma,
+               steps=done, every=every, R_D=RD, omega=w, damping=lam, omega_ms=w_ms,
+               E=abs(w_ms - w) / w_ms, diverged=status != M.OK, wall_s=round(wall, 1))
+    log(f"[oscillation] {model} R={R}: R_D {RD:.2f}, omega {w:.4e} vs Miller-Scriven {w_ms:.4e}: "
+        f"E {100 * out['E']:.2f} %  ({done} steps, {wall:.0f} s{', diverged' if out['diverged'] else ''})")
+    return out
+
+
+def oscillation_table(M, radii=OSC_RADII, models=("CG", "SC"), log=print):
+    """Table dropOsc re-run: every model at every radius, with the printed
+    values beside the measured ones."""
+    rows = []
+    for model in models:
+        for i, R in enumerate(radii):
+            o = oscillation_run(M, model, float(R), log=log)
+            pr = PRINTED_DROPOSC[model][OSC_RADII.index(R)] if R in OSC_RADII else None
+            o["printed"] = dict(R_D=pr[0], omega=pr[1], E_percent=pr[2]) if pr else None
+            rows.append(o)
+    return rows
