@@ -343,6 +343,19 @@ def test_ligament_contraction_table_sets(M):
     assert abs(r["3"] - r["2 matched"]) < 0.25 * r["2 matched"]
 
 
+def test_oscillation_dropOsc_densities_sigma_005(M):
+    """Oscillating droplet with the densities and tau of Table dropOscParams
+    (2.73 / 0.073, tau = 1) at sigma = 0.05, R = 37 in 160 x 160 x 240
+    (studies.oscillation_run, FP64): the l = 2 frequency of the y-axis radius
+    is within 3 % of Miller-Scriven at the fitted R_D (measured 1.2 %), the
+    paper's below-1 % regime for this resolution."""
+    from paper_2110_05197_amd import studies
+    o = studies.oscillation_run(M, "CG", 37.0, sigma=0.05, log=say)
+    assert not o["diverged"]
+    assert abs(o["R_D"] - 39.2) < 1.5, o
+    assert o["E"] < 0.03, o
+
+
 def test_rayleigh_plateau_criterion(M):
     """A periodic jet R0 = 12 with a 0.1 R0 sinusoidal perturbation of
     wavelength lambda (one wavelength per box, 64x64xlambda, CG, sigma via
