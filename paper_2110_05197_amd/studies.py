@@ -233,6 +233,15 @@ def sc_mp_sigma(M, G: float, R: int = 16, steps: int = 20000):
     return m
 
 
+def contraction_scales(rho_R: float, sigma: float, R0: float, L: float, tau_R: float):
+    """Capillary time sqrt(rho_R R0^3 / sigma), Srivastava end speed
+    sqrt(sigma / (rho_R R0)) and Ohnesorge number mu / sqrt(rho_R sigma L)
+    with mu = rho_R (tau_R - 1/2) / 3, as the contraction section defines them."""
+    mu = rho_R * (tau_R - 0.5) / 3.0
+    return (math.sqrt(rho_R * R0 ** 3 / sigma), math.sqrt(sigma / (rho_R * R0)),
+            mu / math.sqrt(rho_R * sigma * L))
+
+
 def contraction_run(M, cfg: dict, span: float = 4.5, fit=(2.0, 4.0)):
     """One ligament of Table contrParams (FP64): the capsule of radius R0 and
     length L along x, its endpoint x_e(t) from the outermost interface
@@ -259,8 +268,7 @@ def contraction_run(M, cfg: dict, span: float = 4.5, fit=(2.0, 4.0)):
                           tau_R=cfg["tau"][0], tau_B=cfg["tau"][1], enhanced_eq=cfg["enhanced"])
         p = M.params_from_sigma(p, sigma)
         fields = inputs.ligament(CONTR_SHAPE, R0, length, rhoR, rhoB, axis=0)
-    tcap = math.sqrt(rhoR * R0 ** 3 / sigma)
-    u_an = math.sqrt(sigma / (rhoR * R0))
+    tcap, u_an, Oh = contraction_scales(rhoR, sigma, R0, length, cfg["tau"][0])
     every = max(2, int(round(tcap / 30.0)))
     s = M.Sim(p)
     s.init_equilibrium(*fields)
@@ -279,10 +287,8 @@ def contraction_run(M, cfg: dict, span: float = 4.5, fit=(2.0, 4.0)):
     ts, xe = np.array(ts), np.array(xe)
     sel = (ts >= fit[0]) & (ts <= fit[1])
     speed = -float(np.polyfit(ts[sel], xe[sel], 1)[0]) if sel.sum() >= 3 else float("nan")
-    mu = rhoR * (cfg["tau"][0] - 0.5) / 3.0
     return dict(set=cfg["name"], model=cfg["model"], rho_R=rhoR, rho_B=rhoB, sigma=sigma, R0=R0, L=length,
-                tau=cfg["tau"], t_cap=tcap, u_analytic=u_an, speed_ratio=speed,
-                Oh=mu / math.sqrt(rhoR * sigma * length), diverged=status != M.OK,
+                tau=cfg["tau"], t_cap=tcap, u_analytic=u_an, speed_ratio=speed, Oh=Oh, diverged=status != M.OK,
                 t=[round(x, 3) for x in ts[::3]], x_end=[round(x, 4) for x in xe[::3]])
 
 

@@ -69,3 +69,18 @@ def test_sc_pressure_equal_at_coexistence_and_flat_at_spinodals():
             r, h = -math.log(x), 1e-6
             slope = (sweeps.sc_pressure(r + h, G) - sweeps.sc_pressure(r - h, G)) / (2 * h)
             assert abs(slope) < 1e-8
+
+
+def test_contraction_sets_reproduce_printed_scales():
+    """The contraction sets as transcribed give the capillary times and
+    Ohnesorge numbers the contraction section prints for them: set 1
+    t_cap = 262.9 and Oh = 0.1, sets 2-4 t_cap = 160 and Oh = 0.084."""
+    sets = {c["name"]: c for c in studies.CONTR_SETS}
+    c = sets["1"]
+    tcap, u, Oh = studies.contraction_scales(c["rho"][0], c["sigma"], c["R0"], c["L"], c["tau"][0])
+    assert abs(tcap - 262.9) < 0.05 and abs(Oh - 0.1) < 0.0005
+    assert abs(u * tcap - c["R0"]) < 1e-9          # the end moves R0 per capillary time
+    for name in ("2", "4"):
+        c = sets[name]
+        tcap, u, Oh = studies.contraction_scales(c["rho"][0], c["sigma"], c["R0"], c["L"], c["tau"][0])
+        assert abs(tcap - 160.0) < 0.5 and abs(Oh - 0.084) < 0.0005
