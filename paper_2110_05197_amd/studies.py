@@ -407,7 +407,8 @@ def osc_box(R: float):
     return (360, 240, 240) if R >= 45 else (240, 160, 160)
 
 
-def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float = 1.25, sigma=None, log=print):
+def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float = 1.25, sigma=None, beta=None,
+                    log=print):
     """One droplet of Table dropOscParams (FP64, tau = 1 in both phases): a
     prolate ellipsoid of volume (4/3) pi R^3 and axis ratio `aspect` along z,
     its y-axis radius R(t) through the box centre from the interface crossings
@@ -415,7 +416,8 @@ def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float
     damped-cosine fit R(t) = R_D + b exp(-l t) cos(w t + ph), and the error of
     w against Miller-Scriven (Eqs. millscriv-millscriv3) at the fitted R_D.
 
-    CG: rho 2.73 / 0.073, sigma 0.183 (or `sigma`).  SC (multiphase): the coupling whose
+    CG: rho 2.73 / 0.073, sigma 0.183 (or `sigma`), recolouring beta 0.7 (or
+    `beta`).  SC (multiphase): the coupling whose
     coexistence has the same density ratio (37.4), densities and sigma from a
     Laplace run of that model (the paper's G = -6 maps to other densities in
     its pseudopotential, R17)."""
@@ -437,6 +439,8 @@ def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float
         (rho_in, rho_out), sigma = OSC_RHO, (OSC_SIGMA if sigma is None else sigma)
         p = M.make_params(lattice=M.D3Q19, precision=M.FP64, nx=nx, ny=ny, nz=nz, rho0_R=rho_in,
                           rho0_B=rho_out, tau_R=1.0, tau_B=1.0)
+        if beta is not None:
+            p["beta"] = float(beta)
         p = M.params_from_sigma(p, sigma)
         fields = inputs.ellipsoid(shape, axes, rho_in, rho_out)
     nu = 1.0 / 6.0
@@ -467,7 +471,9 @@ def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float
     else:
         w = lam = RD = float("nan")
     w_ms = miller_scriven_omega(sigma, RD, rho_in, rho_out, nu, nu) if RD == RD else float("nan")
-    out = dict(model=model if model == "SC" or sigma is None else f"CG sigma={sigma}", R=R, box=[nx, ny, nz], G=G, rho_in=rho_in, rho_out=rho_out, sigma=sigma,
+    label = model if model == "SC" else "CG" + (f" sigma={sigma}" if sigma is not None else "") + (
+        f" beta={beta}" if beta is not None else "")
+    out = dict(model=label, R=R, box=[nx, ny, nz], G=G, rho_in=rho_in, rho_out=rho_out, sigma=sigma,
                steps=done, every=every, R_D=RD, omega=w, damping=lam, omega_ms=w_ms,
                E=abs(w_ms - w) / w_ms, diverged=status != M.OK, wall_s=round(wall, 1))
     log(f"[oscillation] {out['model']} R={R}: R_D {RD:.2f}, omega {w:.4e} vs Miller-Scriven {w_ms:.4e}: "
@@ -475,10 +481,11 @@ def oscillation_run(M, model: str, R: float, periods: float = 5.0, aspect: float
     return out
 
 
-def oscillation_table(M, radii=OSC_RADII, models=("CG", "SC"), cg_sigmas=(0.05,), log=print):
+def oscillation_table(M, radii=OSC_RADII, models=("CG", "SC"), cg_sigmas=(0.05,), cg_betas=(0.5,), log=print):
     """Table dropOsc re-run: every model at every radius, with the printed
     values beside the measured ones; then the CG droplets again at each of
-    `cg_sigmas` (same densities and tau), below the printed sigma."""
+    `cg_sigmas` (same densities and tau), below the printed sigma, and at the
+    printed sigma with each recolouring beta of `cg_betas`."""
     rows = []
     for model in models:
         for R in radii:
@@ -489,4 +496,7 @@ def oscillation_table(M, radii=OSC_RADII, models=("CG", "SC"), cg_sigmas=(0.05,)
     for sg in cg_sigmas:
         for R in radii:
             rows.append(oscillation_run(M, "CG", float(R), sigma=sg, log=log))
+    for b in cg_betas:
+        for R in radii:
+            rows.append(oscillation_run(M, "CG", float(R), beta=b, log=log))
     return rows
