@@ -356,6 +356,19 @@ def test_oscillation_dropOsc_densities_sigma_005(M):
     assert o["E"] < 0.03, o
 
 
+def test_oscillation_dropOsc_printed_frequency_beta_05(M):
+    """Table dropOscParams' colour-gradient droplet at the printed sigma =
+    0.183 (rho 2.73 / 0.073, tau = 1), R = 37, recolouring beta = 0.5
+    (studies.oscillation_run, FP64): stable, and its l = 2 frequency scaled
+    to the printed R_D = 36.97 by R^(-3/2) is within 4 % of the printed
+    omega_2 = 2.97e-3 of Table dropOsc (measured 2.92e-3)."""
+    from paper_2110_05197_amd import studies
+    o = studies.oscillation_run(M, "CG", 37.0, beta=0.5, log=say)
+    assert not o["diverged"]
+    w = o["omega"] * (o["R_D"] / 36.97) ** 1.5
+    assert abs(w - 2.97e-3) / 2.97e-3 < 0.04, (w, o)
+
+
 def test_rayleigh_plateau_criterion(M):
     """A periodic jet R0 = 12 with a 0.1 R0 sinusoidal perturbation of
     wavelength lambda (one wavelength per box, 64x64xlambda, CG, sigma via
