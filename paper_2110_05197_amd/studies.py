@@ -329,15 +329,18 @@ def fit_damped_cosine(t, r, w0):
     from scipy.optimize import curve_fit
     model = lambda t, a, b, lam, w, ph: a + b * np.exp(-lam * t) * np.cos(w * t + ph)
     best = None
-    for ph0 in (0.0, math.pi / 2, math.pi, 3 * math.pi / 2):
-        try:
-            pp, _ = curve_fit(model, t, r, p0=[float(r.mean()), float(r[0] - r.mean()), 1e-4, w0, ph0],
-                              maxfev=20000)
-        except RuntimeError:
-            continue
-        res = float(np.sum((model(t, *pp) - r) ** 2))
-        if best is None or res < best[0]:
-            best = (res, pp)
+    for wf in (1.0, 0.7, 1.4):                     # start near, below and above the expected w
+        for ph0 in (0.0, math.pi / 2, math.pi, 3 * math.pi / 2):
+            try:
+                pp, _ = curve_fit(model, t, r, p0=[float(r.mean()), float(r[0] - r.mean()), 1e-4, wf * w0, ph0],
+                                  maxfev=20000)
+            except RuntimeError:
+                continue
+            if pp[2] < 0:                          # a growing envelope is no damped oscillation
+                continue
+            res = float(np.sum((model(t, *pp) - r) ** 2))
+            if best is None or res < best[0]:
+                best = (res, pp)
     if best is None:
         return float("nan"), float("nan"), float("nan")
     pp = best[1]
