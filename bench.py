@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -183,6 +184,18 @@ def copy_probe(n: int):
     print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4, "launches": 3}))
 
 
+def _finite(x):
+    """The same structure with NaN and infinities as null, so the study and
+    sweep lines are strict JSON (an unfitted or diverged case has no value)."""
+    if isinstance(x, float):
+        return x if math.isfinite(x) else None
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    return x
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,13 +256,13 @@ def main():
             steps = args.study_steps or 40000
             out = dict(study="ligament", runs=[studies.ligament(M, prec, steps=steps, log=log)
                                                for prec in (M.MIXED, M.FP16)])
-        print(json.dumps(out))
+        print(json.dumps(_finite(out)))
         return
     if args.sweep:
         from paper_2110_05197_amd import sweeps
         out = sweeps.run(args.sweep, steps=args.sweep_steps,
                          log=lambda *a: print(*a, file=sys.stderr, flush=True))
-        print(json.dumps(out))
+        print(json.dumps(_finite(out)))
         return
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the "
