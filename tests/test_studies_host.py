@@ -84,3 +84,36 @@ def test_contraction_sets_reproduce_printed_scales():
         c = sets[name]
         tcap, u, Oh = studies.contraction_scales(c["rho"][0], c["sigma"], c["R0"], c["L"], c["tau"][0])
         assert abs(tcap - 160.0) < 0.5 and abs(Oh - 0.084) < 0.0005
+
+
+def test_laplace_measure_recovers_sigma_of_a_built_state():
+    """sweeps.measure on observables built from a known droplet: interface
+    radius R from the red volume, inside/outside densities whose pressure
+    jump (Eq. CGpressure, colour sound speeds from Eq. gamma) is 2 sigma / R
+    gives sigma_cal = sigma and E = |0.01 - sigma| / 0.01; E_kin per area
+    uses the set radius when given."""
+    from paper_2110_05197_amd import sweeps
+    for gamma in (1.0, 37.4, 1000.0):
+        p = dict(alpha_B=0.2, rho0_R=gamma, rho0_B=1.0)
+        aR = 1.0 - 0.8 / gamma
+        cR2, cB2 = (1.0 - aR) / 2.0, 0.4
+        R, sigma, rho_out = 17.0, 0.0123, 1.01
+        rho_in = (rho_out * cB2 + 2.0 * sigma / R) / cR2
+        obs = dict(red_volume=4.0 / 3.0 * math.pi * R ** 3, mass_R=rho_in * 4.0 / 3.0 * math.pi * 15.0 ** 3,
+                   rho_in=rho_in, rho_out=rho_out, ekin=2.5, eps_used=1 - 1e-10)
+        m = sweeps.measure(obs, p, R0=16)
+        assert abs(m["R"] - R) < 1e-12 and abs(m["R_equimolar"] - 15.0) < 1e-12
+        assert abs(m["sigma_cal"] - sigma) < 1e-12
+        assert abs(m["E"] - abs(0.01 - sigma) / 0.01) < 1e-10
+        assert abs(m["ekin_per_area"] - 2.5 / (4.0 * math.pi * 256.0)) < 1e-15
+
+
+def test_sc_laplace_pressure_jump_sign():
+    """The SC equation of state gives a positive Young-Laplace jump for a
+    liquid drop slightly above its coexistence density in slightly
+    compressed vapour, and zero at the flat coexistence pair."""
+    from paper_2110_05197_amd import serve, sweeps
+    G = -5.0
+    liq, gas = serve.sc_coexistence(G)
+    assert abs(sweeps.sc_pressure(liq, G) - sweeps.sc_pressure(gas, G)) < 1e-12
+    assert sweeps.sc_pressure(liq * 1.02, G) - sweeps.sc_pressure(gas, G) > 0
