@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size and launch configuration: D3Q19 CG,
-FP32, fused kernel, 256^3 with the 32-droplet fields.
+FP32, fused kernel, 256^3 with the 32-droplet fields, and the D2Q9 line's
+4096^2 with its 32 disks.
 
 A node's populations after one step depend only on the populations within
 Chebyshev distance 2 (streaming pulls from distance 1, whose collision reads
@@ -62,6 +63,48 @@ def test_fullsize_sampled_nodes_match_oracle(M, orc):
         e = float(np.abs(out[:, :, 2, 2, 2] - f1[:, :, z, y, x].cpu().numpy()).max()) / scale
         worst = max(worst, e)
     say(f"[fullsize] 256^3 fused FP32: worst sampled rel err after 1 step {worst:.2e}")
+    assert worst <= 2e-6
+    del f0, f1
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_d2q9_sampled_nodes_match_oracle(M, orc):
+    """The D2Q9 benchmark line (`bench.py --lattice D2Q9`): 4096^2 with the
+    32-disk fields, FP32, the one-pass row kernel; 32 sampled nodes after one
+    step recomputed by the oracle from their periodic 5x5 neighbourhoods."""
+    import torch
+    sys.path.insert(0, ".")
+    import bench
+    n = 256
+    rR, rB = bench.workload_fields(n, lattice="D2Q9")
+    p = bench.params(n, precision=M.FP32, kernel=M.KERNEL_FUSED, lattice="D2Q9")
+    ny, nx = p["ny"], p["nx"]
+    assert (p["nz"], ny, nx) == (1, 4096, 4096)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB)
+    assert sim.kernel_used() == M.KERNEL_FUSED
+    sim.step(5)
+    f0 = sim.export_f()
+    st, _ = sim.step(1)
+    assert st == M.OK
+    f1 = sim.export_f()
+    rng = np.random.default_rng(6)
+    rho = f0.sum(dim=1)
+    rn = ((rho[0] - rho[1]) / (rho[0] + rho[1]))[0].cpu().numpy()
+    iface = np.argwhere(np.abs(rn) < 0.9)
+    pts = [tuple(iface[i]) for i in rng.choice(len(iface), 24, replace=False)]
+    pts += [(int(rng.integers(0, ny)), int(rng.integers(0, nx))) for _ in range(8)]
+    po = dict(p, nx=5, ny=5, nz=1)
+    worst = 0.0
+    scale = float(f1.abs().max())
+    for (y, x) in pts:
+        iy = [(y + d) % ny for d in range(-2, 3)]
+        ix = [(x + d) % nx for d in range(-2, 3)]
+        box = f0[:, :, :, iy][:, :, :, :, ix].cpu().numpy()
+        out = orc.run(po, box, 1)
+        e = float(np.abs(out[:, :, 0, 2, 2] - f1[:, :, 0, y, x].cpu().numpy()).max()) / scale
+        worst = max(worst, e)
+    say(f"[fullsize] 4096^2 D2Q9 fused FP32: worst sampled rel err after 1 step {worst:.2e}")
     assert worst <= 2e-6
     del f0, f1
     torch.cuda.empty_cache()
