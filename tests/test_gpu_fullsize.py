@@ -30,13 +30,16 @@ def M():
     return M
 
 
-def test_fullsize_sampled_nodes_match_oracle(M, orc):
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (0, 1e-12), (2, 2e-6)])
+def test_fullsize_sampled_nodes_match_oracle(M, orc, prec, tol):
+    """The bench workload at 256^3 in FP32 (the timed configuration), FP64
+    (64x4 columns) and mixed precision, one-pass kernel."""
     import torch
     sys.path.insert(0, ".")
     import bench
     n = 256
     rR, rB = bench.workload_fields(n)
-    p = bench.params(n, precision=M.FP32, kernel=M.KERNEL_FUSED)
+    p = bench.params(n, precision=prec, kernel=M.KERNEL_FUSED)
     sim = M.Sim(p)
     sim.init_equilibrium(rR, rB)
     sim.step(5)                         # leave the initial equilibrium
@@ -62,8 +65,8 @@ def test_fullsize_sampled_nodes_match_oracle(M, orc):
         out = orc.run(po, box, 1)
         e = float(np.abs(out[:, :, 2, 2, 2] - f1[:, :, z, y, x].cpu().numpy()).max()) / scale
         worst = max(worst, e)
-    say(f"[fullsize] 256^3 fused FP32: worst sampled rel err after 1 step {worst:.2e}")
-    assert worst <= 2e-6
+    say(f"[fullsize] 256^3 fused precision {prec}: worst sampled rel err after 1 step {worst:.2e}")
+    assert worst <= tol
     del f0, f1
     torch.cuda.empty_cache()
 
