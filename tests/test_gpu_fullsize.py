@@ -113,6 +113,54 @@ def test_fullsize_d2q9_sampled_nodes_match_oracle(M, orc):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("model", ["SC_MP", "SC_MC"])
+def test_fullsize_shan_chen_sampled_nodes_match_oracle(M, orc, model):
+    """The Shan-Chen bench lines (`bench.py --model SC_MP|SC_MC`): 256^3 of
+    the 32-droplet fields, FP32, one-pass kernel; the forces reach one node
+    and streaming one more, so the 5^3 neighbourhood still holds every
+    dependency of the centre."""
+    import torch
+    sys.path.insert(0, ".")
+    import bench
+    n = 256
+    rR, rB = bench.workload_fields(n, model=model)
+    p = bench.params(n, precision=M.FP32, kernel=M.KERNEL_FUSED, model=model)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB)
+    assert sim.kernel_used() == M.KERNEL_FUSED
+    sim.step(5)
+    f0 = sim.export_f()
+    st, _ = sim.step(1)
+    assert st == M.OK
+    f1 = sim.export_f()
+    rho = f0.sum(dim=1)
+    if model == "SC_MP":
+        mid = 0.5 * (p["rho0_R"] + p["rho0_B"])
+        ind = ((rho[0] - mid) / (p["rho0_R"] - p["rho0_B"])).cpu().numpy()
+        iface = np.argwhere(np.abs(ind) < 0.4)
+    else:
+        rn = ((rho[0] - rho[1]) / (rho[0] + rho[1])).cpu().numpy()
+        iface = np.argwhere(np.abs(rn) < 0.9 * float(np.abs(rn).max()))
+    rng = np.random.default_rng(7)
+    pts = [tuple(iface[i]) for i in rng.choice(len(iface), 24, replace=False)]
+    pts += [tuple(rng.integers(0, n, 3)) for _ in range(8)]
+    po = dict(p, nx=5, ny=5, nz=5)
+    worst = 0.0
+    scale = float(f1.abs().max())
+    for (z, y, x) in pts:
+        iz = [(z + d) % n for d in range(-2, 3)]
+        iy = [(y + d) % n for d in range(-2, 3)]
+        ix = [(x + d) % n for d in range(-2, 3)]
+        box = f0[:, :, iz][:, :, :, iy][:, :, :, :, ix].cpu().numpy()
+        out = orc.run(po, box, 1)
+        e = float(np.abs(out[:, :, 2, 2, 2] - f1[:, :, z, y, x].cpu().numpy()).max()) / scale
+        worst = max(worst, e)
+    say(f"[fullsize] 256^3 {model} fused FP32: worst sampled rel err after 1 step {worst:.2e}")
+    assert worst <= 2e-6
+    del f0, f1
+    torch.cuda.empty_cache()
+
+
 def test_fullsize_invariants_over_bench_steps(M):
     import sys as _s
     _s.path.insert(0, ".")
