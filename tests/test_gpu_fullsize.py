@@ -1,6 +1,7 @@
 """Parity at the benchmark's full size and launch configuration: D3Q19 CG,
-FP32, fused kernel, 256^3 with the 32-droplet fields, and the D2Q9 line's
-4096^2 with its 32 disks.
+fused kernel, 256^3 with the 32-droplet fields (FP32, the timed line, and
+FP64 and mixed precision), the Shan-Chen lines at the same size, and the
+D2Q9 line's 4096^2 with its 32 disks.
 
 A node's populations after one step depend only on the populations within
 Chebyshev distance 2 (streaming pulls from distance 1, whose collision reads
