@@ -31,10 +31,13 @@ def M():
     return M
 
 
-@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (0, 1e-12), (2, 2e-6)])
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (0, 1e-12), (2, 2e-6), (3, 1e-3)])
 def test_fullsize_sampled_nodes_match_oracle(M, orc, prec, tol):
     """The bench workload at 256^3 in FP32 (the timed configuration), FP64
-    (64x4 columns) and mixed precision, one-pass kernel."""
+    (64x4 columns), mixed precision and FP16 storage, one-pass kernel.  FP16:
+    the oracle steps the stored values exactly, so the difference is the
+    rounding of the new deviations to half precision (spacing 2.4e-4 at the
+    largest, about a third; bound 1e-3 of max |f|)."""
     import torch
     sys.path.insert(0, ".")
     import bench
