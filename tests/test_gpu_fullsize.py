@@ -185,3 +185,60 @@ def test_fullsize_invariants_over_bench_steps(M):
     assert dR < 1e-5 and dB < 1e-6
     assert o1["umax"] < 0.05
     assert abs(o1["mom_x"]) + abs(o1["mom_y"]) + abs(o1["mom_z"]) < 1e-6 * o0["mass_B"]
+
+
+def test_near_node_limit_lattice_matches_small_box(M):
+    """The largest lattices the library takes (fewer than 2^31 nodes, 32-bit
+    node offsets within a population): 1280 x 1280 x 1310 = 2,146,304,000
+    nodes, SC multiphase with FP16 storage (172 GB of state), one-pass
+    kernel.  A 32^3 block holding a droplet sits at the highest node offsets,
+    against the last z plane, in a uniform vapour; the same block in a 64^3
+    box must evolve identically, since after 5 steps no node of the block
+    depends on anything beyond 10 nodes from it: equal densities, bit for
+    bit, show that addressing and the periodic wrap at the top of the
+    offset range are right."""
+    import ctypes
+    import gc
+    import torch
+    from paper_2110_05197_amd import inputs, serve
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 215e9:
+        pytest.skip(f"needs about 210 GB of free device memory, {free / 1e9:.0f} GB free")
+    G = -5.0
+    liq, gas = serve.sc_coexistence(G)
+    B = 32
+    rR, rB = inputs.droplet((B, B, B), 6.0, liq, gas)
+    blk = torch.from_numpy(rR + rB)
+
+    def run(nx, ny, nz, at, steps=5):
+        p = M.make_params(lattice=M.D3Q19, model=M.SC_MP, precision=M.FP16, nx=nx, ny=ny, nz=nz, G=G,
+                          tau_R=1.0, rho0_R=liq, rho0_B=gas, kernel=M.KERNEL_FUSED)
+        z0, y0, x0 = at
+        assert z0 + B <= nz and y0 + B <= ny and x0 + B <= nx
+        rho = torch.full((nz, ny, nx), float(gas), dtype=torch.float64, device="cuda")
+        rho[z0:z0 + B, y0:y0 + B, x0:x0 + B] = blk.cuda()
+        s = M.Sim(p)
+        s.init_equilibrium(rho, None)
+        del rho
+        assert s.kernel_used() == M.KERNEL_FUSED
+        st, _ = s.step(steps)
+        assert st == M.OK
+        out = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+        M._check(M.lib().mclbm_moments(s._h, ctypes.c_void_p(out.data_ptr()), None, None), "mclbm_moments")
+        torch.cuda.synchronize()
+        region = out[z0:z0 + B, y0:y0 + B, x0:x0 + B].cpu().numpy()
+        s.close()
+        del out, s
+        gc.collect()
+        torch.cuda.empty_cache()
+        return region
+
+    nx, ny, nz = 1280, 1280, 1310
+    assert nx * ny * nz < 2 ** 31
+    small = run(64, 64, 64, (16, 16, 16))
+    big = run(nx, ny, nz, (nz - B - 1, ny - B - 8, nx - B - 8))
+    say(f"[node limit] {nx * ny * nz} nodes: block max |big - small| = {float(np.abs(big - small).max()):.1e}")
+    assert np.array_equal(big, small)
+    assert small.max() > 1.5 and small.min() < 0.2      # the droplet is there
