@@ -187,13 +187,14 @@ def test_fullsize_invariants_over_bench_steps(M):
     assert abs(o1["mom_x"]) + abs(o1["mom_y"]) + abs(o1["mom_z"]) < 1e-6 * o0["mass_B"]
 
 
-@pytest.mark.parametrize("lattice", ["D3Q19", "D2Q9"])
-def test_near_node_limit_lattice_matches_small_box(M, lattice):
+@pytest.mark.parametrize("lattice,kernel", [("D3Q19", 2), ("D3Q19", 1), ("D2Q9", 2)])
+def test_near_node_limit_lattice_matches_small_box(M, lattice, kernel):
     """The largest lattices the library takes (fewer than 2^31 nodes, 32-bit
     node offsets within a population).  D3Q19: 1280 x 1280 x 1310 =
     2,146,304,000 nodes, SC multiphase with FP16 storage (172 GB of state);
     D2Q9: 46336^2 = 2,147,024,896 nodes, colour gradient with FP16 storage
-    (180 GB); one-pass kernels.  A block holding a droplet (disk) sits at
+    (180 GB); one-pass kernels, and the D3Q19 case on the two-pass kernels
+    too (its density fields addressed at offsets up to 2^31).  A block holding a droplet (disk) sits at
     the highest node offsets, against the last z plane (last row), in a
     uniform ambient; the same block in a 64^3 (64^2) box must evolve
     identically, since after 5 steps no node of the block depends on
@@ -229,7 +230,7 @@ def test_near_node_limit_lattice_matches_small_box(M, lattice):
 
     def run(box, at, steps=5):
         nz, ny, nx = box
-        p = M.make_params(precision=M.FP16, nx=nx, ny=ny, nz=nz, kernel=M.KERNEL_FUSED, **kw)
+        p = M.make_params(precision=M.FP16, nx=nx, ny=ny, nz=nz, kernel=kernel, **kw)
         z0, y0, x0 = at
         assert z0 + bz <= nz and y0 + B <= ny and x0 + B <= nx
         fields = []
@@ -243,7 +244,7 @@ def test_near_node_limit_lattice_matches_small_box(M, lattice):
         s = M.Sim(p)
         s.init_equilibrium(*fields)
         del fields
-        assert s.kernel_used() == M.KERNEL_FUSED
+        assert s.kernel_used() == kernel
         st, _ = s.step(steps)
         assert st == M.OK
         out = torch.empty(box, dtype=torch.float64, device="cuda")
@@ -260,7 +261,7 @@ def test_near_node_limit_lattice_matches_small_box(M, lattice):
     assert nx * ny * nz < 2 ** 31
     small = run(small_box, (16 if bz > 1 else 0, 16, 16))
     big = run(big_box, ((nz - bz - 1) if bz > 1 else 0, ny - B - 1 if bz == 1 else ny - B - 8, nx - B - 8))
-    say(f"[node limit] {lattice} {nx * ny * nz} nodes: block max |big - small| = "
+    say(f"[node limit] {lattice} kernel {kernel} {nx * ny * nz} nodes: block max |big - small| = "
         f"{float(np.abs(big - small).max()):.1e}")
     assert np.array_equal(big, small)
     assert small.max() - small.min() > 0.5              # the droplet is there
