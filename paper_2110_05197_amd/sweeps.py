@@ -119,10 +119,13 @@ def fit_slope(R, y):
     return float(np.polyfit(np.log(R[ok]), np.log(y[ok]), 1)[0])
 
 
-def _batch_run(M, params, fields, steps, chunk, log, label):
+def _batch_run(M, params, fields, steps, chunk, log, label, record_every=None):
     """Advance one batch of droplets `steps` steps (K-step graphs of `chunk`),
     printing progress about every 20 s; returns the sims, their status words
-    and step counts, and the wall time."""
+    and step counts, the wall time and, with `record_every`, the history
+    [(step, [E_kin of each sim])]: the batch then runs in segments of that
+    many steps, closed after each so the members can be read (a diverged
+    member leaves the later segments)."""
     import torch
     stream = torch.cuda.Stream()
     sims = []
@@ -132,19 +135,37 @@ def _batch_run(M, params, fields, steps, chunk, log, label):
             s.init_equilibrium(rR, rB)
             sims.append(s)
     t0 = time.perf_counter()
-    batch = M.Batch(sims, [steps] * len(sims), stream=stream)
+    seg = steps if not record_every else min(int(record_every), steps)
+    counts = [0] * len(sims)
+    bad = [False] * len(sims)
+    history = []
     done, last = 0, t0
     while done < steps:
-        k = min(chunk, steps - done)
-        batch.step(k, use_graph=True)   # diverged droplets stop themselves
-        done += k
-        if time.perf_counter() - last > 20.0:
-            stream.synchronize()
-            last = time.perf_counter()
-            log(f"[sweep] {label}: {done}/{steps} steps, {last - t0:.0f} s")
-    st, counts = batch.status()
-    batch.close()
-    return sims, st, counts, time.perf_counter() - t0
+        k_seg = min(seg, steps - done)
+        alive = [i for i in range(len(sims)) if not bad[i]]
+        if not alive:
+            break
+        batch = M.Batch([sims[i] for i in alive], [k_seg] * len(alive), stream=stream)
+        d = 0
+        while d < k_seg:
+            k = min(chunk, k_seg - d)
+            batch.step(k, use_graph=True)   # diverged droplets stop themselves
+            d += k
+            if time.perf_counter() - last > 20.0:
+                stream.synchronize()
+                last = time.perf_counter()
+                log(f"[sweep] {label}: {done + d}/{steps} steps, {last - t0:.0f} s")
+        st, cnt = batch.status()
+        batch.close()
+        for i, sti, c in zip(alive, st, cnt):
+            counts[i] += int(c)
+            bad[i] = sti == M.STOPPED_DIVERGED
+        done += k_seg
+        if record_every:
+            history.append((done, [s.observables()["ekin"] if not b else float("nan") for s, b in zip(sims, bad)]))
+    status = [M.STOPPED_DIVERGED if b else M.DONE for b in bad]
+    out = (sims, status, counts, time.perf_counter() - t0)
+    return out + (history,) if record_every else out
 
 
 def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=print):
@@ -240,8 +261,25 @@ def sc_measure(sim, p):
                 sigma=dP * R / 2.0, ekin=o["ekin"], diverged=bool(o["diverged"]))
 
 
+def settle_step(history, i, tol=0.05):
+    """First recorded step from which E_kin of sim i stays within `tol` of
+    its last recorded value (the stabilisation of the E_kin-in-time figure
+    of section 3.1.2)."""
+    final = history[-1][1][i]
+    if not final == final or final <= 0:
+        return None
+    first = None
+    for step, ek in history:
+        if abs(ek[i] - final) <= tol * final:
+            if first is None:
+                first = step
+        else:
+            first = None
+    return first
+
+
 def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=EKIN_GAMMA, couplings=GSCAN,
-             taus=(1.0,), log=print):
+             taus=(1.0,), record_every=5000, log=print):
     """The CG and SC stationary droplets as one batch (three groups: CG FP32,
     CG FP64, SC FP64); returns the per-case results and the E_kin fits.
     `taus` lists red relaxation times for the CG droplets (tau_B = 1); with
@@ -262,9 +300,12 @@ def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=E
                 todo.append(("CG", (g, t, sg)))
                 params.append(p)
                 fields.append(inputs.droplet((L, L, L), float(EKIN_R), p["rho0_R"], p["rho0_B"]))
-    sims, st, counts, wall = _batch_run(M, params, fields, steps, chunk, log, "ekin")
+    rec = record_every if record_every and steps >= 4 * record_every else None
+    res = _batch_run(M, params, fields, steps, chunk, log, "ekin", record_every=rec)
+    sims, st, counts, wall = res[:4]
+    history = res[4] if rec else []
     sc_rows, cg_rows = [], []
-    for (kind, key), s, p, stat, n in zip(todo, sims, params, st, counts):
+    for idx, ((kind, key), s, p, stat, n) in enumerate(zip(todo, sims, params, st, counts)):
         bad = stat == M.STOPPED_DIVERGED
         if kind == "SC":
             m = sc_measure(s, p) if not bad else dict(diverged=True)
@@ -274,6 +315,9 @@ def run_ekin(steps: int = 100_000, chunk: int = 500, sigmas=EKIN_SIGMA, gammas=E
             o = s.observables()
             m = dict(gamma=key[0], tau_R=key[1], sigma=key[2], ekin=o["ekin"], steps=int(n),
                      diverged=bool(bad or o["diverged"]))
+            if history:
+                m["settle_step"] = settle_step(history, idx)
+                m["ekin_history"] = [(h[0], h[1][idx]) for h in history]
             if not m["diverged"]:
                 m["sigma_cal"] = measure(o, p)["sigma_cal"]
             cg_rows.append(m)

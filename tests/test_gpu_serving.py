@@ -100,10 +100,12 @@ def test_ekin_sweep_machinery(M):
     for density ratios 1 and 1000, one batch of three groups.  No
     divergence; SC droplets keep densities near the flat coexistence pair of
     their coupling, with a larger density ratio and a larger positive sigma
-    at the stronger coupling; CG spurious-current energy grows with sigma."""
+    at the stronger coupling; CG spurious-current energy grows with sigma;
+    the batch run in four recorded segments keeps each droplet's E_kin
+    history, whose last entry is the final value."""
     from paper_2110_05197_amd import serve, sweeps
     out = sweeps.run_ekin(steps=4000, chunk=500, sigmas=(0.01, 0.1), gammas=(1, 1000), couplings=(-4.8, -5.6),
-                          log=lambda *a: None)
+                          record_every=1000, log=lambda *a: None)
     sc, cg = out["sc"], out["cg"]
     assert len(sc) == 2 and len(cg) == 4
     assert not any(m["diverged"] for m in sc + cg)
@@ -119,6 +121,10 @@ def test_ekin_sweep_machinery(M):
         e = {m["sigma"]: m["ekin"] for m in cg if m["gamma"] == g}
         assert e[0.1] > e[0.01] > 0, (g, e)
     assert set(out["fits"]) == {"SC", "CG gamma=1", "CG gamma=1000"}
+    for m in cg:      # recorded in four segments of 1000 steps; the last equals the final E_kin
+        assert [h[0] for h in m["ekin_history"]] == [1000, 2000, 3000, 4000] and m["steps"] == 4000
+        assert m["ekin_history"][-1][1] == m["ekin"]
+        assert m["settle_step"] in (1000, 2000, 3000, 4000)
 
 
 def test_shortest_work_first_admission(M):
