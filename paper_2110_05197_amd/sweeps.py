@@ -35,7 +35,8 @@ Study "ekin" (the stationary-droplet comparison of CG and SC, section
   total kinetic energy E_kin;
 * colour gradient at sigma_th = 0.001 ... 0.3 for density ratios 1, 10,
   100, 1000 (tau = 1 for both colours; FP32, FP64 from density ratio 100),
-  E_kin at the end;
+  E_kin at the end and every 5000 steps, with the step from which it stays
+  within 5 % of its final value;
 
 and E_kin ∝ sigma^b fitted per series (the paper: b = 2 for CG at every
 density ratio, b = 3.3 for SC, whose density ratio stays below about 50).
