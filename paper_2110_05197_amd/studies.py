@@ -212,7 +212,7 @@ CONTR_SETS = (
     dict(name="1 plain", model="CG", rho=(2.0, 0.1), tau=(1.0, 0.55), sigma=0.05, R0=12.0, L=112.0, enhanced=0),
     dict(name="2", model="CG", rho=(1.99, 0.165), tau=(1.0, 1.0), sigma=0.078, R0=10.0, L=100.0, enhanced=1),
     dict(name="3", model="SC", G=-5.0, tau=(1.0,), R0=10.0, L=100.0),
-    dict(name="2 matched", model="CG", match_sc=True, tau=(1.0, 1.0), R0=10.0, L=100.0, enhanced=1),
+    dict(name="2 matched", model="CG", match_sc=True, G=-5.0, tau=(1.0, 1.0), R0=10.0, L=100.0, enhanced=1),
     dict(name="4", model="CG", rho=(1.99, 0.165), tau=(1.0, 0.55), sigma=0.078, R0=10.0, L=100.0, enhanced=1),
 )
 
@@ -259,8 +259,8 @@ def contraction_run(M, cfg: dict, span: float = 4.5, fit=(2.0, 4.0)):
         rR, rB = inputs.ligament(CONTR_SHAPE, R0, length, rhoR, rhoB, axis=0)
         fields = (rR + rB, None)
     else:
-        if cfg.get("match_sc"):
-            m = sc_mp_sigma(M, -5.0)
+        if cfg.get("match_sc"):      # sigma and densities of the SC model at this G
+            m = sc_mp_sigma(M, cfg["G"])
             rhoR, rhoB, sigma = m["rho_in"], m["rho_out"], m["sigma"]
         else:
             (rhoR, rhoB), sigma = cfg["rho"], cfg["sigma"]
