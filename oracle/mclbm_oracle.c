@@ -22,6 +22,15 @@
  *
  * Readings of passages where the paper is silent or garbled carry the tag
  * "reading:" and are listed, with their reasons, in the design notes.
+ *
+ * Every colour-gradient and Shan-Chen multiphase function here is pinned by a
+ * CPU test against something other than this file (printed constants, moment
+ * identities, closed-form decay rates including the blended viscosity of
+ * Eq. interpVisc, the Laplace law, coexistence densities, invariants).  Parity
+ * unpinned beyond invariants: the two-component Shan-Chen step's blend of
+ * per-component relaxation times with one barycentric velocity (its cross force
+ * is pinned by the demixing threshold), the physical magnitude of the CG
+ * repulsion force, and the multirange Shan-Chen couplings' surface tension.
  */
 #include <math.h>
 #include <stdint.h>

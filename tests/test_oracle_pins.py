@@ -312,6 +312,40 @@ def test_shear_wave_viscous_decay(orc, lattice, shape):
     assert abs(amp / 1e-3 - math.exp(-nu * k * k * steps)) / math.exp(-nu * k * k * steps) < 0.01
 
 
+@pytest.mark.parametrize("lattice,shape", [(0, (1, 64, 3)), (1, (3, 64, 3))])
+@pytest.mark.parametrize("red_fraction", [1.0, 0.0, 0.5, 0.8])
+def test_shear_wave_decays_at_interface_viscosity(orc, lattice, shape, red_fraction):
+    """A uniform mixture of the two colours with tau_R = 0.7, tau_B = 1.3
+    (nu_R = 1/15, nu_B = 4/15).  With uniform colour densities the enhanced
+    equilibrium terms, the perturbation and the recolouring flux all vanish,
+    so the total distribution relaxes by BGK with omega_eff (Eq. effRelax) of
+    the blended viscosity of Eq. interpVisc, 1/nu = (rho_R/rho)/nu_R +
+    (rho_B/rho)/nu_B, and a shear wave decays as exp(-nu k^2 t) with that nu:
+    red alone at nu_R, blue alone at nu_B, the 50/50 mixture at the harmonic
+    mean (4/37.5 = 0.1067, against the arithmetic 0.1667), the 80/20 mixture at
+    1/12.75 = 0.0784 (swapping the weights would give 0.1667)."""
+    tau_R, tau_B = 0.7, 1.3
+    nu_R, nu_B = (tau_R - 0.5) / 3.0, (tau_B - 0.5) / 3.0
+    p = orc.make_params(lattice=lattice, nx=shape[2], ny=shape[1], nz=shape[0], tau_R=tau_R,
+                        tau_B=tau_B, rho0_R=1.0, rho0_B=1.0)
+    u = inputs.shear_wave(shape, 1e-3, axis_u=0, axis_k=1)
+    rR = np.full(shape, red_fraction)
+    rB = np.full(shape, 1.0 - red_fraction)
+    f = orc.init_equilibrium(p, rR, rB, u)
+    steps = 400
+    f1 = orc.run(p, f, steps)
+    r1R, r1B, j = orc.moments(p, f1)
+    # the colour densities stay uniform (the wave is divergence free)
+    assert np.abs(r1R - red_fraction).max() < 1e-6
+    ux = j[0] / (r1R + r1B)
+    k = 2 * np.pi / shape[1]
+    prof = np.sin(k * np.arange(shape[1]))
+    amp = (ux.mean(axis=(0, 2)) * prof).sum() / (prof * prof).sum()
+    nu = 1.0 / (red_fraction / nu_R + (1.0 - red_fraction) / nu_B)
+    expect = math.exp(-nu * k * k * steps)
+    assert abs(amp / 1e-3 - expect) / expect < 0.01, (amp / 1e-3, expect)
+
+
 def test_laplace_d2q9_static_droplet(orc):
     """64x64 periodic D2Q9, R = 16, gamma = 1, tau = 1, A = 0.01, beta = 0.7,
     2000 steps.  Young-Laplace in 2D, dP = sigma / R, with p_k = rho_k c_s^2
