@@ -184,6 +184,17 @@ mclbm_status mclbm_state_bytes(const mclbm_params *p, size_t *bytes);
  * once and written once): 2 * ncomp * Q * sizeof(storage). */
 mclbm_status mclbm_bytes_per_update(const mclbm_params *p, double *bytes);
 
+/* Layout of the population buffers inside the state (host only; for tests
+ * and diagnostics: callers never index the state themselves).  A buffer
+ * holds *arrays population arrays of *word_bytes-byte words (a word is one
+ * population of one node; two-colour FP16 storage keeps both colours of a
+ * population in one 4-byte word), each array *words words from the previous
+ * one.  *words >= N: arrays of large lattices are padded so that the arrays
+ * of one buffer do not start a multiple of a large power of two apart (the
+ * streams of a step would then fall on the same HBM banks).  EINVAL on NULL
+ * or invalid parameters. */
+mclbm_status mclbm_population_stride(const mclbm_params *p, int64_t *words, int32_t *word_bytes, int32_t *arrays);
+
 /* Create a simulation on caller memory d_state (>= mclbm_state_bytes, not
  * freed by the library), enqueuing on `stream`.  Allocates the library's
  * small scratch on the current device.  The state is undefined until

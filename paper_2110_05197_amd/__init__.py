@@ -14,7 +14,8 @@ import ctypes
 import os
 
 __all__ = ["MclbmError", "Sim", "Batch", "lib", "make_params", "params_default",
-           "params_from_sigma", "sigma_from_params", "state_bytes", "bytes_per_update", "version",
+           "params_from_sigma", "sigma_from_params", "state_bytes", "bytes_per_update", "population_stride",
+           "version",
            "D2Q9", "D3Q19", "CG", "SC_MP", "SC_MC", "FP64", "FP32", "MIXED", "FP16",
            "PERIODIC", "WALL", "OUTFLOW", "KERNEL_AUTO", "KERNEL_TWO_PASS", "KERNEL_FUSED",
            "OK", "DIVERGED", "RUNNING", "DONE", "STOPPED_DIVERGED"]
@@ -91,6 +92,8 @@ def lib():
             "mclbm_sigma_from_params": [_P, ctypes.POINTER(ctypes.c_double)],
             "mclbm_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
             "mclbm_bytes_per_update": [_P, ctypes.POINTER(ctypes.c_double)],
+            "mclbm_population_stride": [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)],
             "mclbm_create": [_P, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)],
             "mclbm_destroy": [_vp],
             "mclbm_init_equilibrium": [_vp, _vp, _vp, _vp],
@@ -202,6 +205,15 @@ def bytes_per_update(p: dict) -> float:
     out = ctypes.c_double()
     _check(lib().mclbm_bytes_per_update(ctypes.byref(s), ctypes.byref(out)), "mclbm_bytes_per_update")
     return out.value
+
+
+def population_stride(p: dict):
+    """(words between population arrays, bytes per word, arrays per buffer)."""
+    s = _to_struct(p)
+    w, b, a = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mclbm_population_stride(ctypes.byref(s), ctypes.byref(w), ctypes.byref(b), ctypes.byref(a)),
+           "mclbm_population_stride")
+    return w.value, b.value, a.value
 
 
 def _torch():

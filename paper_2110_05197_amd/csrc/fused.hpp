@@ -103,7 +103,7 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
     FT (*lds)[NF][PL] = reinterpret_cast<FT (*)[NF][PL]>(smem);
     C *pop = reinterpret_cast<C *>(smem + fused_ring_bytes<LA, MODEL, TX, TY, FT>());
 
-    const long long N = P.N;
+    const long long SW = P.S;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const HP<C, M> H = make_hp<C, M>(P);
     const int tid = threadIdx.x;
@@ -152,11 +152,11 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
         C tmp[K][Q];
         M d2[2], j2[3];
         if (act) {
-            load_node<L, K>(src, N, n_xy + zoff(z0 - 1), tmp);
+            load_node<L, K>(src, SW, n_xy + zoff(z0 - 1), tmp);
             put(z0 - 1, my_slot, tmp, d2, j2, true);
-            load_node<L, K>(src, N, n_xy + zoff(z0), c);
+            load_node<L, K>(src, SW, n_xy + zoff(z0), c);
             put(z0, my_slot, c, drc, jc, true);
-            load_node<L, K>(src, N, n_xy + zoff(z0 + 1), tmp);
+            load_node<L, K>(src, SW, n_xy + zoff(z0 + 1), tmp);
             put(z0 + 1, my_slot, tmp, drn, jn, true);
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -165,7 +165,7 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
         }
         if (has_h)
             for (int p = z0 - 1; p <= z0 + 1; ++p) {
-                load_node<L, K>(src, N, h_xy + zoff(p), tmp);
+                load_node<L, K>(src, SW, h_xy + zoff(p), tmp);
                 put(p, h_slot, tmp, d2, j2, false);
             }
     }
@@ -176,8 +176,8 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
         const bool ahead = z + 2 <= z1;
         RawNode<L, K, typename Prec<PR>::S, C> dr_, hr_;
         if (ahead) {
-            if (act) dr_.load(src, N, n_xy + zoff(z + 2));
-            if (has_h) hr_.load(src, N, h_xy + zoff(z + 2));
+            if (act) dr_.load(src, SW, n_xy + zoff(z + 2));
+            if (has_h) hr_.load(src, SW, h_xy + zoff(z + 2));
         }
 
         // 2. collide plane z with the stencil values of planes z-1, z, z+1

@@ -18,7 +18,7 @@ __device__ __forceinline__ double node_phase64(const KParams &P, const typename 
 {
     constexpr int K = NComp<MODEL>::n;
     double g[K][L::Q];
-    load_node<L, K>(f, P.N, n, g);
+    load_node<L, K>(f, P.S, n, g);
     double dr[2], j[3];
     node_moments<L, K>(g, dr, j);
     const double rR = P.rho0[0] + dr[0];

@@ -47,22 +47,24 @@ template <bool NT, class T> __device__ __forceinline__ void st(T *p, T v)
 using Half2 = _Float16 __attribute__((ext_vector_type(2)));
 template <int K, class S> constexpr bool kPairs = K == 2 && std::is_same<S, _Float16>::value;
 
+// SW: storage words from one population array to the next (KParams::S).
 template <class L, int K, class S>
-__device__ __forceinline__ size_t sidx(int k, int i, size_t N, size_t n)
+__device__ __forceinline__ size_t sidx(int k, int i, size_t SW, size_t n)
 {
-    if constexpr (kPairs<K, S>) return 2 * ((size_t)i * N + n) + (size_t)k;
-    else return (size_t)(k * L::Q + i) * N + n;
+    if constexpr (kPairs<K, S>) return 2 * ((size_t)i * SW + n) + (size_t)k;
+    else return (size_t)(k * L::Q + i) * SW + n;
 }
 
+// Populations of node n; SW is the array stride KParams::S.
 template <class L, int K, class S, class C, bool NT = false>
-__device__ __forceinline__ void load_node(const S *__restrict__ f, long long N, long long n,
+__device__ __forceinline__ void load_node(const S *__restrict__ f, long long SW, long long n,
                                           C (&g)[K][L::Q])
 {
     const unsigned o = (unsigned)n;   // N < 2^31: per-lane 32-bit offset, uniform base
     if constexpr (kPairs<K, S>) {
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            const Half2 v = ld<NT>(&(reinterpret_cast<const Half2 *>(f) + (size_t)i * (size_t)N)[o]);
+            const Half2 v = ld<NT>(&(reinterpret_cast<const Half2 *>(f) + (size_t)i * (size_t)SW)[o]);
             g[0][i] = (C)v.x;
             g[1][i] = (C)v.y;
         }
@@ -70,7 +72,7 @@ __device__ __forceinline__ void load_node(const S *__restrict__ f, long long N, 
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) g[k][i] = (C)ld<NT>(&(f + (size_t)(k * L::Q + i) * (size_t)N)[o]);
+            for (int i = 0; i < L::Q; ++i) g[k][i] = (C)ld<NT>(&(f + (size_t)(k * L::Q + i) * (size_t)SW)[o]);
     }
 }
 
@@ -80,9 +82,9 @@ __device__ __forceinline__ void load_node(const S *__restrict__ f, long long N, 
 template <class L, int K, class S, class C, bool PAIRS = kPairs<K, S>>
 struct RawNode {
     C v[K][L::Q];
-    __device__ __forceinline__ void load(const S *__restrict__ f, long long N, long long n)
+    __device__ __forceinline__ void load(const S *__restrict__ f, long long SW, long long n)
     {
-        load_node<L, K>(f, N, n, v);
+        load_node<L, K>(f, SW, n, v);
     }
     __device__ __forceinline__ void get(C (&g)[K][L::Q]) const
     {
@@ -95,10 +97,10 @@ struct RawNode {
 template <class L, int K, class S, class C>
 struct RawNode<L, K, S, C, true> {
     Half2 v[L::Q];
-    __device__ __forceinline__ void load(const S *__restrict__ f, long long N, long long n)
+    __device__ __forceinline__ void load(const S *__restrict__ f, long long SW, long long n)
     {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) v[i] = (reinterpret_cast<const Half2 *>(f) + (size_t)i * (size_t)N)[(unsigned)n];
+        for (int i = 0; i < L::Q; ++i) v[i] = (reinterpret_cast<const Half2 *>(f) + (size_t)i * (size_t)SW)[(unsigned)n];
     }
     __device__ __forceinline__ void get(C (&g)[K][L::Q]) const
     {
@@ -112,17 +114,17 @@ struct RawNode<L, K, S, C, true> {
 
 // Population i of every colour of g stored into slot j of node t.
 template <class L, int K, class S, class C, bool NT>
-__device__ __forceinline__ void store_pop(S *__restrict__ dst, size_t N, unsigned t, int j, int i,
+__device__ __forceinline__ void store_pop(S *__restrict__ dst, size_t SW, unsigned t, int j, int i,
                                           const C (&g)[K][L::Q])
 {
     if constexpr (kPairs<K, S>) {
         Half2 v;
         v.x = (S)g[0][i];
         v.y = (S)g[1][i];
-        st<NT>(&(reinterpret_cast<Half2 *>(dst) + (size_t)j * N)[t], v);
+        st<NT>(&(reinterpret_cast<Half2 *>(dst) + (size_t)j * SW)[t], v);
     } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) st<NT>(&(dst + (size_t)(k * L::Q + j) * N)[t], (S)g[k][i]);
+        for (int k = 0; k < K; ++k) st<NT>(&(dst + (size_t)(k * L::Q + j) * SW)[t], (S)g[k][i]);
     }
 }
 
@@ -136,7 +138,7 @@ template <class L, int K, class S, class C, bool NTA = false>
 __device__ __forceinline__ void push_store_general(const KParams &P, S *__restrict__ dst, int x, int y, int z,
                                                    long long n, const C (&g)[K][L::Q])
 {
-    const size_t N = (size_t)P.N;
+    const size_t SW = (size_t)P.S;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         int kind = 0;
@@ -145,11 +147,11 @@ __device__ __forceinline__ void push_store_general(const KParams &P, S *__restri
         const int tz = push_coord(z + L::cz[i], P.nz, P.bc[2], kind);
         const int o = i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
         if (kind & 1) {
-            store_pop<L, K, S, C, false>(dst, N, (unsigned)n, o, i, g);
+            store_pop<L, K, S, C, false>(dst, SW, (unsigned)n, o, i, g);
         } else if (kind == 0) {
             const unsigned t = (unsigned)tx + (unsigned)P.nx * ((unsigned)ty + (unsigned)P.ny * (unsigned)tz);
-            if (NTA && L::cx[i] == 0) store_pop<L, K, S, C, true>(dst, N, t, i, i, g);
-            else store_pop<L, K, S, C, false>(dst, N, t, i, i, g);
+            if (NTA && L::cx[i] == 0) store_pop<L, K, S, C, true>(dst, SW, t, i, i, g);
+            else store_pop<L, K, S, C, false>(dst, SW, t, i, i, g);
         }
     }
 }
@@ -160,7 +162,7 @@ template <class L, int K, class S, class C, bool NTA = false>
 __device__ __forceinline__ void push_store_periodic(const KParams &P, S *__restrict__ dst, int x, int y, int z,
                                                     long long n, const C (&g)[K][L::Q])
 {
-    const size_t N = (size_t)P.N;
+    const size_t N = (size_t)P.N, SW = (size_t)P.S;
     const int nx = P.nx, sxy = P.nx * P.ny;
     const int dxp = x == P.nx - 1 ? 1 - nx : 1, dxm = x == 0 ? nx - 1 : -1;
     const int dyp = y == P.ny - 1 ? nx - sxy : nx, dym = y == 0 ? sxy - nx : -nx;
@@ -172,8 +174,8 @@ __device__ __forceinline__ void push_store_periodic(const KParams &P, S *__restr
         if (L::cy[i]) d += L::cy[i] > 0 ? dyp : dym;
         if (L::cz[i]) d += L::cz[i] > 0 ? dzp : dzm;
         const unsigned t = (unsigned)((int)n + d);
-        if (NTA && L::cx[i] == 0) store_pop<L, K, S, C, true>(dst, N, t, i, i, g);
-        else store_pop<L, K, S, C, false>(dst, N, t, i, i, g);
+        if (NTA && L::cx[i] == 0) store_pop<L, K, S, C, true>(dst, SW, t, i, i, g);
+        else store_pop<L, K, S, C, false>(dst, SW, t, i, i, g);
     }
 }
 
@@ -199,7 +201,7 @@ __device__ __forceinline__ bool density_body(const KParams &P, const typename Pr
     using FT = typename Prec<PR>::F;
     constexpr int K = NComp<MODEL>::n;
     C g[K][L::Q];
-    load_node<L, K>(f, P.N, n, g);
+    load_node<L, K>(f, P.S, n, g);
     M dr[2], j[3];
     node_moments<L, K>(g, dr, j);
     const HP<C, M> H = make_hp<C, M>(P);
@@ -333,7 +335,7 @@ __device__ __forceinline__ void collide_body(const KParams &P, const typename Pr
     const int x = (int)(n % P.nx), y = (int)((n / P.nx) % P.ny), z = (int)(n / ((long long)P.nx * P.ny));
     const HP<C, M> H = make_hp<C, M>(P);
     C g[K][L::Q];
-    load_node<L, K>(src, N, n, g);
+    load_node<L, K>(src, P.S, n, g);
     M dr[2], j[3];
     node_moments<L, K>(g, dr, j);
     long long nb[L::Q];
@@ -408,7 +410,7 @@ __device__ __forceinline__ void collide_body(const KParams &P, const typename Pr
 template <class L, int K, class S>
 __device__ __forceinline__ void outflow_body(const KParams &P, S *__restrict__ dst, int x, int y, int z)
 {
-    const long long N = P.N;
+    const long long SW = P.S;
     const long long n = (long long)x + (long long)P.nx * ((long long)y + (long long)P.ny * z);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
@@ -424,7 +426,7 @@ __device__ __forceinline__ void outflow_body(const KParams &P, S *__restrict__ d
         if (P.bc[2] == 2 && (z - L::cz[i] < 0 || z - L::cz[i] >= P.nz)) iz += z == 0 ? 1 : -1;
         const long long m = (long long)ix + (long long)P.nx * ((long long)iy + (long long)P.ny * iz);
 #pragma unroll
-        for (int k = 0; k < K; ++k) dst[sidx<L, K, S>(k, i, N, n)] = dst[sidx<L, K, S>(k, i, N, m)];
+        for (int k = 0; k < K; ++k) dst[sidx<L, K, S>(k, i, SW, n)] = dst[sidx<L, K, S>(k, i, SW, m)];
     }
 }
 
@@ -489,15 +491,15 @@ __device__ __forceinline__ void init_body(const KParams &P, const double *__rest
         const double rR = rhoR[n], rB = rhoB[n], r = rR + rB;
         const double nub = 1.0 / ((rR / r) * P.inv_nu[0] + (rB / r) * P.inv_nu[1]);
         for (int i = 0; i < L::Q; ++i) {
-            f[sidx<L, 2, S>(0, i, N, n)] = (S)cg_eq_dev<L>(P, 0, i, rR, u, gR, nub);
-            f[sidx<L, 2, S>(1, i, N, n)] = (S)cg_eq_dev<L>(P, 1, i, rB, u, gB, nub);
+            f[sidx<L, 2, S>(0, i, P.S, n)] = (S)cg_eq_dev<L>(P, 0, i, rR, u, gR, nub);
+            f[sidx<L, 2, S>(1, i, P.S, n)] = (S)cg_eq_dev<L>(P, 1, i, rB, u, gB, nub);
         }
     } else if constexpr (MODEL == SC_MP) {
-        for (int i = 0; i < L::Q; ++i) f[sidx<L, 1, S>(0, i, N, n)] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
+        for (int i = 0; i < L::Q; ++i) f[sidx<L, 1, S>(0, i, P.S, n)] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
     } else {
         for (int i = 0; i < L::Q; ++i) {
-            f[sidx<L, 2, S>(0, i, N, n)] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
-            f[sidx<L, 2, S>(1, i, N, n)] = (S)sc_eq_dev<L>(P, 1, i, rhoB[n], u);
+            f[sidx<L, 2, S>(0, i, P.S, n)] = (S)sc_eq_dev<L>(P, 0, i, rhoR[n], u);
+            f[sidx<L, 2, S>(1, i, P.S, n)] = (S)sc_eq_dev<L>(P, 1, i, rhoB[n], u);
         }
     }
 }
@@ -514,7 +516,7 @@ __device__ __forceinline__ bool node_state64(const KParams &P, const typename Pr
     constexpr int K = NComp<MODEL>::n;
     const long long N = P.N;
     double g[K][L::Q];
-    load_node<L, K>(f, N, n, g);
+    load_node<L, K>(f, P.S, n, g);
     double dr[2];
     node_moments<L, K>(g, dr, j);
     rR = P.rho0[0] + dr[0];

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_export(KParams P, const typename Pre
     for (int k = 0; k < K; ++k)
         for (int i = 0; i < L::Q; ++i) {
             const long long a = (long long)(k * L::Q + i) * P.N + n;
-            out[a] = (double)f[sidx<L, K, typename Prec<PR>::S>(k, i, P.N, n)] + P.shift[k][L::grp[i]];
+            out[a] = (double)f[sidx<L, K, typename Prec<PR>::S>(k, i, P.S, n)] + P.shift[k][L::grp[i]];
         }
 }
 
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams P, const double *__re
     for (int k = 0; k < K; ++k)
         for (int i = 0; i < L::Q; ++i) {
             const long long a = (long long)(k * L::Q + i) * P.N + n;
-            f[sidx<L, K, typename Prec<PR>::S>(k, i, P.N, n)] = (typename Prec<PR>::S)(in[a] - P.shift[k][L::grp[i]]);
+            f[sidx<L, K, typename Prec<PR>::S>(k, i, P.S, n)] = (typename Prec<PR>::S)(in[a] - P.shift[k][L::grp[i]]);
         }
 }
 

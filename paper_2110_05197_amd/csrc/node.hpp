@@ -30,7 +30,8 @@ template <> struct Prec<3> { using S = _Float16; using C = float;  using M = flo
 struct KParams {
     int nx, ny, nz;
     int bc[3];
-    long long N;
+    long long N;         // nodes
+    long long S;         // storage words from one population array to the next (>= N)
     int enhanced;
     int has_outflow;
     double rho0[2];      // reference densities of the deviation storage
