@@ -282,6 +282,20 @@ mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged);
 mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
                                        int32_t max, int32_t *count);
 mclbm_status mclbm_plane_area(mclbm_sim *sim, int32_t axis, int32_t pos, double *area);
+
+/* mclbm_interface_crossings for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving or measurement loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernels and results,
+ * but it calls no hipMalloc, hipFree or other allocating routine.  Its
+ * scratch (the sampled line, the positions, the count) is a static device
+ * array of 2 * 32768 + 16 doubles (512 KB) that every device holds for the
+ * life of the process; the first call on a device looks up its address.
+ * EUNSUPPORTED for a line longer than 32768 nodes.  All calls on one device
+ * share that array: calls that overlap on one device (other host threads,
+ * other streams) race and must be serialised by the caller.  Synchronises
+ * the simulation's stream, like mclbm_interface_crossings. */
+mclbm_status mclbm_interface_crossings_noalloc(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
+                                               int32_t max, int32_t *count);
 mclbm_status mclbm_droplets(mclbm_sim *sim, int32_t max, int32_t *count, int64_t *h_sizes);
 
 /* The step kernel this simulation runs: MCLBM_KERNEL_FUSED (one pass:

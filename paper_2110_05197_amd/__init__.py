@@ -110,6 +110,9 @@ def lib():
             "mclbm_interface_crossings": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)],
+            "mclbm_interface_crossings_noalloc": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_int32)],
             "mclbm_plane_area": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
             "mclbm_droplets": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int64)],
@@ -361,13 +364,15 @@ class Sim:
         _check(lib().mclbm_diverged(self._h, ctypes.byref(d)), "mclbm_diverged")
         return bool(d.value)
 
-    def interface_crossings(self, axis: int, c1: int, c2: int, max_out: int = 64):
+    def interface_crossings(self, axis: int, c1: int, c2: int, max_out: int = 64, noalloc: bool = False):
         """Interpolated interface positions along the lattice line parallel to
-        `axis` through (c1, c2) (the other coordinates, in axis order), ascending."""
+        `axis` through (c1, c2) (the other coordinates, in axis order), ascending.
+        noalloc: the allocation-free entry point (static device scratch, lines
+        of up to 32768 nodes)."""
         out = (ctypes.c_double * max(1, max_out))()
         n = ctypes.c_int32()
-        _check(lib().mclbm_interface_crossings(self._h, axis, c1, c2, out, max_out, ctypes.byref(n)),
-               "mclbm_interface_crossings")
+        name = "mclbm_interface_crossings_noalloc" if noalloc else "mclbm_interface_crossings"
+        _check(getattr(lib(), name)(self._h, axis, c1, c2, out, max_out, ctypes.byref(n)), name)
         return [out[i] for i in range(min(n.value, max_out))], n.value
 
     def plane_area(self, axis: int, pos: int) -> float:

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1088,8 +1089,9 @@ static mclbm_status iface_buffers(mclbm_sim *sim)
     return MCLBM_OK;
 }
 
-mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
-                                       int32_t max, int32_t *count)
+// Arguments of the two interface-crossing calls.
+static mclbm_status crossings_args(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, const double *h_pos,
+                                   int32_t max, const int32_t *count)
 {
     mclbm_status s = check_sim(sim);
     if (s) return s;
@@ -1098,8 +1100,17 @@ mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1,
     const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
     if (c1 < 0 || c1 >= axis_len(sim, a1) || c2 < 0 || c2 >= axis_len(sim, a2))
         return fail(MCLBM_EINVAL, "line (%d, %d) outside the box", c1, c2);
-    s = iface_buffers(sim);
-    if (s) return s;
+    return MCLBM_OK;
+}
+
+// Crossings along a line (arguments checked), with device scratch `buf` of at
+// least 2 * (line length) + 9 doubles: the sampled indicator, the positions
+// and the count.
+static mclbm_status crossings_on(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos, int32_t max,
+                                 int32_t *count, double *buf)
+{
+    mclbm_status s;
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
     const long long nx = sim->prm.nx, sxy = nx * sim->prm.ny;
     const long long stride[3] = {1, nx, sxy};
     const int len = axis_len(sim, axis);
@@ -1109,8 +1120,8 @@ mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1,
     ns.s2 = 0;
     ns.len1 = len;
     ns.count = len;
-    double *line = sim->d_iface, *out = sim->d_iface + len + 8;
-    int *d_count = (int *)(sim->d_iface + 2 * len + 8);
+    double *line = buf, *out = buf + len + 8;
+    int *d_count = (int *)(buf + 2 * len + 8);
     const int keep = std::min(max, len);
     sim->ops->phase_sample(sim->kp, sim->f[sim->cur], ns, line, sim->stream);
     hipLaunchKernelGGL(k_crossings, dim3(1), dim3(256), 0, sim->stream, line, len,
@@ -1124,6 +1135,62 @@ mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1,
         MCLBM_HIP(hipMemcpy(h_pos, out, sizeof(double) * (size_t)std::min(n, keep), hipMemcpyDeviceToHost));
     *count = n;
     return MCLBM_OK;
+}
+
+mclbm_status mclbm_interface_crossings(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
+                                       int32_t max, int32_t *count)
+{
+    mclbm_status s = crossings_args(sim, axis, c1, c2, h_pos, max, count);
+    if (s) return s;
+    s = iface_buffers(sim);
+    if (s) return s;
+    return crossings_on(sim, axis, c1, c2, h_pos, max, count, sim->d_iface);
+}
+
+// Scratch of the allocation-free crossing call: a line of up to
+// kNoAllocLine nodes (sampled indicator, positions, count).  Each device
+// holds its own copy for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr int kNoAllocLine = 32768;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[2 * kNoAllocLine + 16];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_at[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller's current device is restored).
+static mclbm_status scratch_on(int device, double **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(MCLBM_EUNSUPPORTED, "device %d", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_at[device]) {
+        int cur = 0;
+        MCLBM_HIP(hipGetDevice(&cur));
+        if (cur != device) MCLBM_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) MCLBM_HIP(hipSetDevice(cur));
+        if (e != hipSuccess) return fail(MCLBM_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_at[device] = (double *)p;
+    }
+    *ptr = g_scratch_at[device];
+    return MCLBM_OK;
+}
+
+mclbm_status mclbm_interface_crossings_noalloc(mclbm_sim *sim, int32_t axis, int32_t c1, int32_t c2, double *h_pos,
+                                               int32_t max, int32_t *count)
+{
+    mclbm_status s = crossings_args(sim, axis, c1, c2, h_pos, max, count);
+    if (s) return s;
+    const int len = axis_len(sim, axis);
+    if (len > kNoAllocLine)
+        return fail(MCLBM_EUNSUPPORTED, "line of %d nodes: the allocation-free call holds at most %d", len,
+                    kNoAllocLine);
+    double *buf = nullptr;
+    s = scratch_on(sim->device, &buf);
+    if (s) return s;
+    return crossings_on(sim, axis, c1, c2, h_pos, max, count, buf);
 }
 
 mclbm_status mclbm_plane_area(mclbm_sim *sim, int32_t axis, int32_t pos, double *area)
