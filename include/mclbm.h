@@ -304,6 +304,13 @@ mclbm_status mclbm_droplets(mclbm_sim *sim, int32_t max, int32_t *count, int64_t
  * NULL. */
 mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel);
 
+/* Work of one block of the one-pass kernel: a *tx x *ty column of nodes
+ * marching through *tz planes (D3Q19), or a row segment of *tx nodes marching
+ * through *tz rows (D2Q9, *ty = 1); blocks at the end of the lattice march
+ * fewer.  Host only; EUNSUPPORTED when the simulation runs the two-pass
+ * kernels, EINVAL on NULL. */
+mclbm_status mclbm_fused_tile(const mclbm_sim *sim, int32_t *tx, int32_t *ty, int32_t *tz);
+
 /* ------------------------------------------------------------------------ */
 /* Batched stepping of many independent simulations (sweep serving).         */
 /* ------------------------------------------------------------------------ */

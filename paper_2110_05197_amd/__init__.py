@@ -107,6 +107,7 @@ def lib():
             "mclbm_restore": [_vp, _vp, ctypes.c_int64],
             "mclbm_diverged": [_vp, ctypes.POINTER(ctypes.c_int32)],
             "mclbm_kernel_used": [_vp, ctypes.POINTER(ctypes.c_int32)],
+            "mclbm_fused_tile": [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 3,
             "mclbm_interface_crossings": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)],
@@ -392,6 +393,13 @@ class Sim:
         k = ctypes.c_int32()
         _check(lib().mclbm_kernel_used(self._h, ctypes.byref(k)), "mclbm_kernel_used")
         return k.value
+
+    def fused_tile(self):
+        """(tx, ty, planes): the column (or row segment) and march length of one
+        block of the one-pass kernel."""
+        v = [ctypes.c_int32() for _ in range(3)]
+        _check(lib().mclbm_fused_tile(self._h, *[ctypes.byref(x) for x in v]), "mclbm_fused_tile")
+        return tuple(x.value for x in v)
 
 
 class Batch:

@@ -482,12 +482,20 @@ inline KParams as_marching_2d(const KParams &P)
     return Q;
 }
 
+// Row segments and rows per block of the 2-D launch (Q: the box as
+// nx x 1 x ny).
+inline void fused2d_rows(const KParams &Q, int &tiles_x, int &tz)
+{
+    tiles_x = (Q.nx + k2dTX - 1) / k2dTX;
+    const int tiles_z = std::max(1, std::min(512 / tiles_x, Q.nz / 8));
+    tz = (Q.nz + tiles_z - 1) / tiles_z;
+}
+
 template <int PR, int MODEL, bool RAGGED>
 void launch_fused2d_shape(const KParams &Q, const void *src, void *dst, unsigned *flag, hipStream_t s)
 {
-    const int tiles_x = (Q.nx + k2dTX - 1) / k2dTX;
-    const int tiles_z = std::max(1, std::min(512 / tiles_x, Q.nz / 8));
-    const int tz = (Q.nz + tiles_z - 1) / tiles_z;
+    int tiles_x = 0, tz = 0;
+    fused2d_rows(Q, tiles_x, tz);
     const dim3 grid(tiles_x * ((Q.nz + tz - 1) / tz)), block(k2dTX);
     using S = typename Prec<PR>::S;
     constexpr int lds = fused_lds_bytes<PR, MODEL, k2dTX, 1, D2Q9Z>();

@@ -708,6 +708,26 @@ mclbm_status mclbm_kernel_used(const mclbm_sim *sim, int32_t *kernel)
     return MCLBM_OK;
 }
 
+mclbm_status mclbm_fused_tile(const mclbm_sim *sim, int32_t *tx, int32_t *ty, int32_t *tz)
+{
+    if (!sim || !tx || !ty || !tz) return fail(MCLBM_EINVAL, "null argument");
+    if (!sim->fused) return fail(MCLBM_EUNSUPPORTED, "the simulation runs the two-pass kernels");
+    if (sim->prm.lattice == MCLBM_D2Q9) {
+        int tiles_x = 0, rows = 0;
+        fused2d_rows(as_marching_2d(sim->kp), tiles_x, rows);
+        *tx = k2dTX;
+        *ty = 1;
+        *tz = rows;
+    } else {
+        FusedShape sh;
+        fused_shape(sim->kp, sh, sim->prm.precision == MCLBM_FP64);
+        *tx = sh.tx;
+        *ty = sh.ty;
+        *tz = sh.tz;
+    }
+    return MCLBM_OK;
+}
+
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged)
 {
     if (!sim || !diverged) return fail(MCLBM_EINVAL, "NULL argument");

@@ -118,7 +118,7 @@ def test_cg_d3q19_fp32(M, orc, kernel):
 
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_cg_d3q19_fp32_density_ratio_tile_shapes(M, orc, kernel):
-    # nx = 96: the fused kernel uses 32-wide tiles; ny = 20: 4-row tiles
+    # nx = 96: a 64-wide column and a masked 32-wide edge column; ny = 20: 4-row tiles
     shape = (18, 20, 96)
     p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=96, ny=20, nz=18, A=0.02,
                       rho0_B=0.1, tau_R=0.8, tau_B=1.0)
@@ -154,6 +154,62 @@ def test_mixed_beats_fp32_at_density_ratio_1000(M, orc):
         say(f"    prec={prec} rel err f={res[prec][0]:.3e} light-phase rho abs err={eB:.3e}")
     assert res[1][0] <= 2e-5 and res[2][0] <= 2e-5
     assert res[2][1] <= res[1][1] * 1.01
+
+
+# --------------------------------------------------------------------------
+# The one-pass kernel as the benchmark runs it: every block marches many
+# planes (the plane-(z+2) prefetch, the four-plane LDS ring and the rotation
+# through the per-thread slot all execute), 100 steps against the oracle.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,bc,tol,min_planes", [(1, (0, 0, 0), 2e-5, 8), (0, (0, 0, 0), 1e-10, 16),
+                                                    (1, (1, 1, 2), 2e-5, 8), (0, (1, 1, 2), 1e-10, 16),
+                                                    (2, (0, 0, 0), 2e-5, 8)])
+def test_cg_d3q19_deep_march(M, orc, prec, bc, tol, min_planes):
+    """256 x 64 x 64, density ratio 10, droplet with 1 % density and 0.02
+    velocity noise: 4 x 8 columns of 64 x 8 (64 x 4 in FP64), so each block
+    marches 8 (16) planes."""
+    shape = (64, 64, 256)
+    p = M.make_params(lattice=M.D3Q19, precision=prec, nx=256, ny=64, nz=64, bc=bc, A=0.02,
+                      rho0_B=0.1, tau_R=0.8, tau_B=1.0)
+    rR, rB, u = cg_droplet_case(shape, 41, gamma=10.0)
+    if bc[2] == 2:
+        u[2] += 0.01
+    sim = M.Sim(dict(p, kernel=2))
+    tx, ty, planes = sim.fused_tile()
+    say(f"[deep march] prec={prec} bc={bc}: {tx}x{ty} columns, {planes} planes per block")
+    assert planes >= min_planes
+    compare(M, orc, p, rR, rB, u, 100, tol, kernel=2, label="cg-d3q19-deep-march")
+
+
+def test_cg_d2q9_fp32_row_kernel(M, orc):
+    """D2Q9 FP32 at 1024 x 512 = 2^19 nodes, where the automatic choice is
+    the one-pass row kernel (rows of 256 marching along y), 100 steps."""
+    shape = (1, 512, 1024)
+    p = M.make_params(lattice=M.D2Q9, precision=M.FP32, nx=1024, ny=512, nz=1, A=0.02, rho0_B=0.5,
+                      tau_R=0.7, tau_B=1.0)
+    rR, rB, u = cg_droplet_case(shape, 42, gamma=2.0, lattice=0)
+    sim = M.Sim(p)
+    assert sim.kernel_used() == M.KERNEL_FUSED
+    tx, ty, rows = sim.fused_tile()
+    say(f"[d2q9 row kernel] {tx}-node row segments, {rows} rows per block")
+    assert rows >= 8
+    compare(M, orc, p, rR, rB, u, 100, 2e-5, label="cg-d2q9-fp32-row-kernel")
+
+
+@pytest.mark.parametrize("prec", [1, 0, 2, 3])
+def test_deep_march_fused_equals_two_pass_bitwise(M, prec):
+    """The one-pass kernel with 8-16 planes per block equals the two-pass
+    kernels bit for bit (colour gradient, periodic and walls + outflow)."""
+    shape = (64, 64, 256)
+    for bc in ((0, 0, 0), (1, 1, 2)):
+        p = M.make_params(lattice=M.D3Q19, precision=prec, nx=256, ny=64, nz=64, bc=bc, A=0.02,
+                          rho0_B=0.1, tau_R=0.8, tau_B=1.0)
+        rR, rB, u = cg_droplet_case(shape, 43, gamma=10.0)
+        say(f"[bitwise deep march] prec={prec} bc={bc}")
+        s1, f1 = gpu_run(M, p, rR, rB, u, 29, kernel=1)
+        s2, f2 = gpu_run(M, p, rR, rB, u, 29, kernel=2)
+        assert s2.fused_tile()[2] >= 8
+        assert np.array_equal(f1, f2)
 
 
 # --------------------------------------------------------------------------
