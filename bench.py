@@ -107,17 +107,23 @@ def params(n: int, precision: int = 1, kernel: int = 0, model: str = "CG", latti
 
 def stream_probe(n: int):
     """Ceilings of the step's memory pattern: the committed stream probe (built
-    next to the library) moving one FP32 D3Q19 step's bytes in each pattern."""
+    next to the library) moving one FP32 D3Q19 step's bytes in each pattern,
+    with the population arrays n^3 floats apart and then padded as the
+    library pads them."""
     import subprocess
+    import paper_2110_05197_amd as M
     exe = os.path.join(ROOT, "paper_2110_05197_amd", "stream_probe")
     if not os.path.exists(exe):
         print("bench.py: stream_probe is not built (run __graft_entry__.build())", file=sys.stderr)
         sys.exit(1)
-    r = subprocess.run([exe, str(n)], capture_output=True, text=True, timeout=600)
-    sys.stdout.write(r.stdout)
-    if r.returncode:
-        sys.stderr.write(r.stderr)
-        sys.exit(r.returncode)
+    words, _, _ = M.population_stride(params(n))
+    for pad in (0, words - n ** 3):
+        r = subprocess.run([exe, str(n), "20", str(pad)], capture_output=True, text=True, timeout=600)
+        sys.stdout.write(r.stdout)
+        sys.stdout.flush()
+        if r.returncode:
+            sys.stderr.write(r.stderr)
+            sys.exit(r.returncode)
 
 
 def cpu_baseline(rR, rB, n: int, steps: int):

@@ -81,18 +81,20 @@ size_t pop_arrays(const mclbm_params &p)
 // array is 64 MB) the 38 concurrent streams of a step fall on the same HBM
 // banks: measured on MI355X, the one-pass 256^3 FP32 colour-gradient step
 // took 1.18 ms with 64 MB between arrays and 1.12 ms with 64 MB + 64 KB +
-// 512 B (in a timing copy of the step, exactly 64 KB or 128 KB extra were
-// slower than none, 16-512 KB plus 256-512 B all faster).  Arrays of 8 MB and more
-// therefore start 64 KB + 512 B past a 1 MB boundary of the previous one's
-// end; smaller ones (which the 256 MB Infinity Cache largely holds) are only
-// rounded to 256 B, plus 512 B.
+// 512 B or 64 MB + 256 KB + 256 B (in a timing copy of the step, exactly
+// 64 KB or 128 KB extra were slower than none), and a plain sweep reading and
+// writing every population at its node rose from 0.67 to 0.74 of the HBM
+// peak with 256 KB + 256 B.  Arrays of 8 MB and more therefore start
+// 256 KB + 256 B past a 1 MB boundary of the previous one's end; smaller
+// ones (which the 256 MB Infinity Cache largely holds) are only rounded to
+// 256 B, plus 256 B.
 long long pop_stride(const mclbm_params &p)
 {
     const size_t w = pop_word(p);
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     size_t b = N * w;
-    if (b >= ((size_t)8 << 20)) b = ((b + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1)) + ((size_t)64 << 10) + 512;
-    else b = align256(b) + 512;
+    if (b >= ((size_t)8 << 20)) b = ((b + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1)) + ((size_t)256 << 10) + 256;
+    else b = align256(b) + 256;
     return (long long)(b / w);
 }
 

@@ -30,6 +30,11 @@
 //   *-ldsK           : the same kernel with K KB of (unused) dynamic LDS per
 //                      block, capping the blocks a compute unit holds at once
 //   copy-float4-gs   : float4 copy by 2048 blocks looping over the array
+//   march-*-TXxTY    : the one-pass step's schedule without its stencil and
+//                      arithmetic: each block owns a TX x TY column and walks
+//                      its half of the planes (two chunks in z), loading plane
+//                      z+1 while storing plane z, aligned or pushed (c_x = 0
+//                      stores non-temporal); periodic wrap at the faces
 // Population arrays are `stride` = n^3 + pad floats apart (pad from the command
 // line, a multiple of 64): with pad = 0 and n a power of two every array
 // starts at the same offset modulo a large power of two.  Nodes are kept one
@@ -246,6 +251,54 @@ __global__ __launch_bounds__(256) void copy4_gs(const float4 *__restrict__ a, fl
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = a[i];
 }
 
+// z-march of a TX x TY column over planes [z0, z0 + n/2): the one-pass step's
+// schedule with its loads and stores only.
+template <int TX, int TY, bool PUSH>
+__global__ __launch_bounds__(TX *TY) void march(const float *__restrict__ src, float *__restrict__ dst, int n,
+                                                long long S)
+{
+    const int tiles_x = n / TX, tiles_y = n / TY;
+    const int nb = (int)gridDim.x;
+    const int t = nb % 8 ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (nb / 8) + (int)blockIdx.x / 8;
+    const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
+    const int x = bx * TX + (int)threadIdx.x % TX, y = by * TY + (int)threadIdx.x / TX;
+    const int z0 = bz * (n / 2), z1 = z0 + n / 2;
+    const int sxy = n * n, N = n * n * n;
+    float c[2 * Q], d[2 * Q];
+    auto ld = [&](int z, float (&v)[2 * Q]) {
+        const unsigned o = (unsigned)(x + n * (y + n * z));
+#pragma unroll
+        for (int i = 0; i < 2 * Q; ++i) v[i] = (src + (size_t)i * (size_t)S)[o];
+    };
+    ld(z0, c);
+    for (int z = z0; z < z1; ++z) {
+        if (z + 1 < z1) ld(z + 1, d);
+        const int nn = x + n * (y + n * z);
+        const int dxp = x == n - 1 ? 1 - n : 1, dxm = x == 0 ? n - 1 : -1;
+        const int dyp = y == n - 1 ? n - sxy : n, dym = y == 0 ? sxy - n : -n;
+        const int dzp = z == n - 1 ? sxy - N : sxy, dzm = z == 0 ? N - sxy : -sxy;
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 2 * Q; ++i) s += c[i];
+#pragma unroll
+        for (int i = 0; i < 2 * Q; ++i) {
+            const int q = i % Q;
+            int dd = 0;
+            if (PUSH) {
+                if (CX[q]) dd += CX[q] > 0 ? dxp : dxm;
+                if (CY[q]) dd += CY[q] > 0 ? dyp : dym;
+                if (CZ[q]) dd += CZ[q] > 0 ? dzp : dzm;
+            }
+            float *p = &(dst + (size_t)i * (size_t)S)[(unsigned)(nn + dd)];
+            const float w = scale(c[i], s);
+            if (!PUSH || CX[q] == 0) __builtin_nontemporal_store(w, p);
+            else *p = w;
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * Q; ++i) c[i] = d[i];
+    }
+}
+
 // Lane-layout check of the two rotates: out[l] = from_left(l), out[64 + l] = from_right(l).
 __global__ __launch_bounds__(64) void rotate_check(float *out)
 {
@@ -267,8 +320,8 @@ int main(int argc, char **argv)
     const int nx = argc > 1 ? std::atoi(argv[1]) : 256;
     const int reps = argc > 2 ? std::atoi(argv[2]) : 20;
     const long long pad = argc > 3 ? std::atoll(argv[3]) : 0;
-    if (nx < 64 || nx > 512 || nx % 64 || reps < 1 || pad < 0 || pad % 64 || pad > (1 << 22)) {
-        std::fprintf(stderr, "usage: stream_probe [n (multiple of 64, 64..512)] [repetitions] [pad (multiple of 64)]\n");
+    if (nx < 128 || nx > 512 || nx % 128 || reps < 1 || pad < 0 || pad % 64 || pad > (1 << 22)) {
+        std::fprintf(stderr, "usage: stream_probe [n (multiple of 128, 128..512)] [repetitions] [pad (multiple of 64)]\n");
         return 2;
     }
     const long long N = (long long)nx * nx * nx, sxy = (long long)nx * nx, S = N + pad;
@@ -411,6 +464,30 @@ int main(int argc, char **argv)
         run("tiled-256-row-push-x4", [&](float *x, float *y) {
             hipLaunchKernelGGL(tiled_row_push, dim3((unsigned)((rhi - rlo + 3) / 4)), blk, 0, 0, x, y, nx, rlo, rhi);
         });
+    }
+    {
+        const dim3 b512(512);
+        auto mgrid = [&](int tx, int ty) { return dim3((unsigned)((nx / tx) * (nx / ty) * 2)); };
+        run("march-aligned-64x8", [&](float *x, float *y) {
+            hipLaunchKernelGGL((march<64, 8, false>), mgrid(64, 8), b512, 0, 0, x, y, nx, S);
+        });
+        run("march-push-64x8", [&](float *x, float *y) {
+            hipLaunchKernelGGL((march<64, 8, true>), mgrid(64, 8), b512, 0, 0, x, y, nx, S);
+        });
+        run("march-aligned-128x4", [&](float *x, float *y) {
+            hipLaunchKernelGGL((march<128, 4, false>), mgrid(128, 4), b512, 0, 0, x, y, nx, S);
+        });
+        run("march-push-128x4", [&](float *x, float *y) {
+            hipLaunchKernelGGL((march<128, 4, true>), mgrid(128, 4), b512, 0, 0, x, y, nx, S);
+        });
+        if (nx % 256 == 0) {
+            run("march-aligned-256x2", [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<256, 2, false>), mgrid(256, 2), b512, 0, 0, x, y, nx, S);
+            });
+            run("march-push-256x2", [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<256, 2, true>), mgrid(256, 2), b512, 0, 0, x, y, nx, S);
+            });
+        }
     }
     CHECK(hipFree(a));
     CHECK(hipFree(b));

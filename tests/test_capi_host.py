@@ -80,7 +80,7 @@ def test_state_bytes_layout(M):
     align = lambda b: (b + 255) // 256 * 256
     S, w, arrays = M.population_stride(p)
     assert (w, arrays) == (4, 38)
-    assert S * w == align(N * 4) + 512   # small lattices: 256-byte rounding plus 512 B
+    assert S * w == align(N * 4) + 256   # small lattices: 256-byte rounding plus 256 B
     f = arrays * S * w
     field = 3 * N * 4
     assert M.state_bytes(p) == 2 * align(f) + align(field)
@@ -92,7 +92,7 @@ def test_state_bytes_layout(M):
     (1, 0, 1, (256, 256, 256), 4, 38), (1, 0, 0, (128, 128, 512), 8, 38), (1, 0, 3, (160, 160, 160), 4, 19),
     (1, 1, 3, (256, 256, 256), 2, 19), (0, 0, 1, (1, 4096, 4096), 4, 18), (1, 0, 2, (384, 96, 96), 4, 38)])
 def test_population_stride_padding(M, lattice, model, prec, shape, word, arrays):
-    """Population arrays of 8 MB and more start 64 KB + 512 B past a 1 MB
+    """Population arrays of 8 MB and more start 256 KB + 256 B past a 1 MB
     boundary of the previous array's end, so that no two arrays of a buffer
     start a multiple of a large power of two apart (a 256^3 FP32 array is
     exactly 64 MB)."""
@@ -103,8 +103,8 @@ def test_population_stride_padding(M, lattice, model, prec, shape, word, arrays)
     N = nx * ny * nz
     b = N * w
     assert b >= 8 << 20
-    assert S * w == (b + (1 << 20) - 1) // (1 << 20) * (1 << 20) + (64 << 10) + 512
-    assert (S * w) % (1 << 20) == (64 << 10) + 512
+    assert S * w == (b + (1 << 20) - 1) // (1 << 20) * (1 << 20) + (256 << 10) + 256
+    assert (S * w) % (1 << 20) == (256 << 10) + 256
 
 
 @pytest.mark.parametrize("bad", [
