@@ -329,12 +329,12 @@ mclbm_status mclbm_fused_tile(const mclbm_sim *sim, int32_t *tx, int32_t *ty, in
  * number of further steps sim s should take; a sim stops when it reaches
  * its target or diverges.  Sims must not be stepped on their own while in a
  * batch.  D3Q19 sims that have a one-pass kernel (no repulsion force, no
- * multirange forces), not in mixed precision, with nx % 64 == 0 and
- * ny % 8 == 0 (ny % 4 == 0 in FP64), and whose kernel is not
- * MCLBM_KERNEL_TWO_PASS, step in one batched
- * one-pass launch per group (64 x 8 columns, 64 x 4 in FP64, z-chunks sized
- * for the group); the
- * others in batched two-pass launches.  The per-node arithmetic is the same
+ * multirange forces), with nx % 64 == 0 and ny % 8 == 0 (ny % 4 == 0 in FP64
+ * and mixed precision), and whose kernel is not MCLBM_KERNEL_TWO_PASS, step
+ * in batched one-pass launches (one per boundary kind present in the group:
+ * all faces periodic, or not; 64 x 8 columns, 64 x 4 in FP64 and mixed
+ * precision; z-chunks sized for the group); the others in batched two-pass
+ * launches.  The per-node arithmetic is the same
  * as mclbm_step's, so a sim's result is bitwise the same alone (either
  * kernel) and in any batch. */
 mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t *target_steps,

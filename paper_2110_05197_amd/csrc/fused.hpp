@@ -292,21 +292,24 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
 }
 
 // Batched one-pass step: the blocks of all eligible simulations of a group
-// (D3Q19, nx a multiple of 64, ny of the column height) in one launch; a
-// block finds its simulation in the descriptor array (one-pass block
-// ranges), skips it unless it is running, and processes one column of that
-// simulation, with the periodic push when all its boundaries are periodic
-// and the boundary-aware push otherwise.  The per-node arithmetic is the
-// solo kernels', so a batched simulation evolves bitwise as it would alone.
-// Columns as in the solo kernel: 64-wide rows (at 16 or 32 nodes the rows of
-// the x-shifted pushes split cache lines between neighbouring blocks and the
-// step runs at half speed), 8 rows (4 in FP64), one block per compute unit.
-// No masked edge columns here (the batched two-pass kernels were as fast on
-// the ragged sizes measured, 96^3 and 160^3), and no mixed-precision variant:
-// with its two inlined column variants (periodic and boundary-aware push) it
-// spills registers and runs behind the batched two-pass kernels.
+// (D3Q19, nx a multiple of 64, ny of the column height) in one launch per
+// boundary kind; a block finds its simulation in the descriptor array
+// (one-pass block ranges), skips it unless it is running and of the launch's
+// kind (all faces periodic, or not), and processes one column of that
+// simulation.  The per-node arithmetic is the solo kernels', so a batched
+// simulation evolves bitwise as it would alone.  Columns: 64-wide rows (at 16
+// or 32 nodes the rows of the x-shifted pushes split cache lines between
+// neighbouring blocks and the step runs at half speed), 8 rows (4 in FP64 and
+// in mixed precision, whose FP64 sums need the registers).  One kernel per
+// boundary kind keeps a single column body per kernel: with both inlined the
+// mixed-precision kernel needed 270 registers (one wave per SIMD) and ran no
+// faster than the batched two-pass kernels.  No masked edge columns here (the
+// batched two-pass kernels were as fast on the ragged sizes measured, 96^3 and
+// 160^3).
 constexpr int kBatchTX = 64;
-constexpr int batch_ty(int precision) { return precision == 0 ? 4 : 8; }
+constexpr int batch_ty(int precision) { return precision == 0 || precision == 2 ? 4 : 8; }
+// which kernels a group launches: bit 0 all-periodic sims, bit 1 others
+constexpr int kFusedPeriodic = 1, kFusedBounded = 2;
 
 __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long b)
 {
@@ -318,7 +321,7 @@ __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long
     return lo;
 }
 
-template <int PR, int MODEL>
+template <int PR, int MODEL, bool PERIODIC>
 __global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, int nsims)
 {
     constexpr int kBatchTY = batch_ty(PR);
@@ -326,6 +329,7 @@ __global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, i
     const int s = find_sim_fused(D, nsims, blockIdx.x);
     const SimDesc &d = D[s];
     if (d.state != 0) return;
+    if ((d.P.bc[0] == 0 && d.P.bc[1] == 0 && d.P.bc[2] == 0) != PERIODIC) return;
     const long long b = blockIdx.x - d.fblock0;
     const int tiles_x = d.P.nx / kBatchTX, tiles_y = d.P.ny / kBatchTY;
     const int bx = (int)(b % tiles_x), by = (int)((b / tiles_x) % tiles_y), bz = (int)(b / ((long long)tiles_x * tiles_y));
@@ -334,10 +338,7 @@ __global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, i
     const S *src = global_ptr<const S>(d.f[d.cur]);
     S *dst = global_ptr<S>(d.f[d.cur ^ 1]);
     unsigned *flag = global_ptr<unsigned>(d.flag);
-    if (d.P.bc[0] == 0 && d.P.bc[1] == 0 && d.P.bc[2] == 0)
-        fused_column<PR, MODEL, kBatchTX, kBatchTY, true>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
-    else
-        fused_column<PR, MODEL, kBatchTX, kBatchTY, false>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
+    fused_column<PR, MODEL, kBatchTX, kBatchTY, PERIODIC>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
 // Planes per column of the batched simulations of a group.  A column
@@ -376,30 +377,46 @@ inline int batch_group_tz(const long long *cols, const int *nz, int n, long long
     return best;
 }
 
-// Blocks of kb_fused<PR, MODEL> the device holds at once.
+// Blocks of kb_fused<PR, MODEL, *> the device holds at once (the smaller of
+// the two boundary kinds).
 template <int PR, int MODEL>
 long long batch_fused_resident()
 {
     constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, batch_ty(PR)>();
-    (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_fused<PR, MODEL>, kBatchTX * batch_ty(PR), lds)
-            != hipSuccess || hipGetDevice(&dev) != hipSuccess
+    int dev = 0, cus = 0, per_cu = 1 << 30;
+    if (hipGetDevice(&dev) != hipSuccess
         || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 256;
+    const void *fns[2] = {(const void *)kb_fused<PR, MODEL, true>, (const void *)kb_fused<PR, MODEL, false>};
+    for (const void *fn : fns) {
+        int b = 0;
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, kBatchTX * batch_ty(PR), lds) != hipSuccess)
+            return 256;
+        per_cu = std::min(per_cu, b);
+    }
     return (long long)std::max(1, per_cu) * std::max(1, cus);
 }
 
+// kinds: kFusedPeriodic and/or kFusedBounded, the boundary kinds present.
 template <int PR, int MODEL>
-void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s)
+void launch_batch_fused(SimDesc *D, int n, long long fblocks, int kinds, hipStream_t s)
 {
     constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, batch_ty(PR)>();
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds);
+        (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((kb_fused<PR, MODEL>), dim3((unsigned)fblocks), dim3(kBatchTX * batch_ty(PR)), lds, s, D, n);
+    if (kinds & kFusedPeriodic)
+        hipLaunchKernelGGL((kb_fused<PR, MODEL, true>), dim3((unsigned)fblocks), dim3(kBatchTX * batch_ty(PR)), lds,
+                           s, D, n);
+    if (kinds & kFusedBounded)
+        hipLaunchKernelGGL((kb_fused<PR, MODEL, false>), dim3((unsigned)fblocks), dim3(kBatchTX * batch_ty(PR)), lds,
+                           s, D, n);
 }
 
 struct FusedShape {

@@ -495,6 +495,7 @@ struct mclbm_batch {
         const Ops *ops;
         int first, count;
         long long blocks, fblocks, oblocks;
+        int fused_kinds;   // kFusedPeriodic | kFusedBounded: boundary kinds of its one-pass sims
         bool any_outflow;
     };
     std::vector<Group> groups;
@@ -933,6 +934,7 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         g.count = (int)groups[key].size();
         g.blocks = 0;
         g.fblocks = 0;
+        g.fused_kinds = 0;
         g.oblocks = 0;
         g.any_outflow = false;
         const long long resident = g.ops->batch_fused_resident();
@@ -965,6 +967,9 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
                 d.fnblocks = (long long)(s->prm.nx / kBatchTX) * (s->prm.ny / batch_ty(s->prm.precision))
                              * ((s->prm.nz + d.ftz - 1) / d.ftz);
                 g.fblocks += d.fnblocks;
+                const bool periodic = s->prm.bc[0] == MCLBM_PERIODIC && s->prm.bc[1] == MCLBM_PERIODIC
+                                      && s->prm.bc[2] == MCLBM_PERIODIC;
+                g.fused_kinds |= periodic ? kFusedPeriodic : kFusedBounded;
             } else {
                 d.nblocks = grid_of(s->kp.N);
                 g.blocks += d.nblocks;
@@ -1030,7 +1035,7 @@ static hipError_t batch_enqueue(mclbm_batch *b, int k)
         }
         for (size_t g = 0; g < G; ++g) {
             const auto &gr = b->groups[g];
-            gr.ops->batch_step(b->d_desc + gr.first, gr.count, gr.blocks, gr.fblocks, gr.oblocks,
+            gr.ops->batch_step(b->d_desc + gr.first, gr.count, gr.blocks, gr.fblocks, gr.fused_kinds, gr.oblocks,
                                gr.any_outflow, g == 0 ? b->stream : b->side[g - 1]);
         }
         for (size_t g = 1; g < G; ++g) {

@@ -29,7 +29,7 @@ struct Ops {
                      int nblocks, hipStream_t s) const = 0;
     // batched step over a group of descriptors: `blocks` two-pass blocks,
     // `fblocks` one-pass blocks, `oblocks` outflow blocks
-    virtual void batch_step(SimDesc *D, int n, long long blocks, long long fblocks, long long oblocks,
+    virtual void batch_step(SimDesc *D, int n, long long blocks, long long fblocks, int fused_kinds, long long oblocks,
                             bool any_outflow, hipStream_t s) const = 0;
     // interface observables: phase indicator of a node set, per-block red
     // fraction partial sums over a node set, initial component labels
@@ -57,18 +57,17 @@ template <class L, int PR, int MODEL, bool REP> constexpr bool fused_available()
 {
     return (L::Q == 19 || L::Q == 9) && !REP;
 }
-// Batched one-pass step (fused.hpp): D3Q19, not for the mixed-precision
-// path (2).
+// Batched one-pass step (fused.hpp): D3Q19.
 template <class L, int PR, int MODEL, bool REP> constexpr bool batch_fused_available()
 {
-    return fused_available<L, PR, MODEL, REP>() && L::Q == 19 && PR != 2;
+    return fused_available<L, PR, MODEL, REP>() && L::Q == 19;
 }
 template <int PR, int MODEL>
 void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);
 template <int PR, int MODEL>
 void launch_fused2d(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s);
 template <int PR, int MODEL>
-void launch_batch_fused(SimDesc *D, int n, long long fblocks, hipStream_t s);
+void launch_batch_fused(SimDesc *D, int n, long long fblocks, int kinds, hipStream_t s);
 template <int PR, int MODEL>
 long long batch_fused_resident();
 
@@ -156,8 +155,8 @@ struct OpsT final : Ops {
         hipLaunchKernelGGL((k_phase_labels<L, PR, MODEL>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
                            (const S *)f, labels);
     }
-    void batch_step(SimDesc *D, int n, long long blocks, long long fblocks, long long oblocks, bool any_outflow,
-                    hipStream_t s) const override
+    void batch_step(SimDesc *D, int n, long long blocks, long long fblocks, int fused_kinds, long long oblocks,
+                    bool any_outflow, hipStream_t s) const override
     {
         if (blocks > 0) {
             hipLaunchKernelGGL((kb_density<L, PR, MODEL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
@@ -166,7 +165,7 @@ struct OpsT final : Ops {
             hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
         }
         if constexpr (batch_fused_available<L, PR, MODEL, REP>()) {
-            if (fblocks > 0) launch_batch_fused<PR, MODEL>(D, n, fblocks, s);
+            if (fblocks > 0) launch_batch_fused<PR, MODEL>(D, n, fblocks, fused_kinds, s);
         }
         if (any_outflow && oblocks > 0)
             hipLaunchKernelGGL((kb_outflow<L, PR, MODEL>), dim3((unsigned)oblocks), dim3(kBlock), 0, s, D, n);

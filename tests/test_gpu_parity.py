@@ -478,13 +478,14 @@ def test_batch_invariance_bitwise(M):
 
 
 def test_batch_one_pass_bitwise(M):
-    """Batched one-pass columns (64 x 8, 64 x 4 in FP64) beside batched
-    two-pass sims (nx not a multiple of 64, ny not a multiple of the column
-    height, mixed precision, repulsion, pinned two-pass, D2Q9) in the same
-    batch: every
-    sim ends bitwise equal to its solo two-pass run; every precision, all
-    three models, walls and outflow, z-chunks with a shorter last chunk (nz =
-    101 is prime: every chunk length above one leaves a remainder)."""
+    """Batched one-pass columns (64 x 8, 64 x 4 in FP64 and mixed precision)
+    beside batched two-pass sims (nx not a multiple of 64, ny not a multiple
+    of the column height, repulsion, pinned two-pass, D2Q9) in the same
+    batch: every sim ends bitwise equal to its solo two-pass run; every
+    precision, all three models, walls and outflow, periodic and bounded sims
+    of one group (two launches of the one-pass kernel), z-chunks with a
+    shorter last chunk (nz = 101 is prime: every chunk length above one leaves
+    a remainder)."""
     def sc_mp(shape):
         a, b = inputs.droplet(shape, 3.0, 1.9, 0.12)
         return a + b, None, None
@@ -494,7 +495,11 @@ def test_batch_one_pass_bitwise(M):
         (M.make_params(lattice=D3, precision=M.FP32, nx=64, ny=16, nz=20, A=0.02), None, 23, F),
         (M.make_params(lattice=D3, precision=M.FP64, nx=64, ny=12, nz=101, A=0.02, bc=(1, 0, 2)), None, 17, F),
         (M.make_params(lattice=D3, precision=M.FP16, nx=64, ny=8, nz=16, A=0.02, bc=(0, 1, 0)), None, 21, F),
-        (M.make_params(lattice=D3, precision=M.MIXED, nx=128, ny=16, nz=16, A=0.02, rho0_B=0.01), None, 19, T),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=128, ny=16, nz=16, A=0.02, rho0_B=0.01), None, 19, F),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=64, ny=12, nz=20, A=0.02, rho0_B=0.01, bc=(1, 1, 2)),
+         None, 16, F),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=64, ny=6, nz=8, A=0.02, rho0_B=0.01), None, 12, T),
+        (M.make_params(lattice=D3, model=M.SC_MC, precision=M.MIXED, nx=64, ny=8, nz=16, G_RB=1.2), None, 22, F),
         (M.make_params(lattice=D3, model=M.SC_MP, precision=M.FP32, nx=64, ny=8, nz=24, G=-5.0, rho0_R=1.9,
                        rho0_B=0.12), "scmp", 25, F),
         (M.make_params(lattice=D3, model=M.SC_MC, precision=M.FP32, nx=64, ny=8, nz=16, G_RB=1.2,
