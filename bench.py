@@ -163,19 +163,24 @@ def serving_leg(full: bool):
     # the full trace runs for minutes: report each finished request
     log = (lambda s: print(s, file=sys.stderr, flush=True)) if full else None
     trace = serve.make_trace(seed=0, **kw)
-    server = serve.Server(k_steps=100, log=log)
+    server = serve.Server(k_steps=100, log=log, keep_fields=True)
     done, wall = server.run(trace)
     batched = serve.summarize(done, wall)
     print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
     trace2 = serve.make_trace(seed=0, **kw)
-    done2, wall2 = serve.serve_one_at_a_time(trace2, log=log)
+    done2, wall2 = serve.serve_one_at_a_time(trace2, log=log, keep_fields=True)
     fifo = serve.summarize(done2, wall2)
     print(f"[bench] one-at-a-time FP64: {fifo}", file=sys.stderr, flush=True)
     agree = sum(1 for a, b in zip(sorted(done, key=lambda r: r.rid), sorted(done2, key=lambda r: r.rid))
                 if a.outcome == b.outcome)
-    return dict(trace=desc, batched=batched, one_at_a_time_fp64=fifo,
+    serve.compare_runs(done, done2)
+    acc = serve.accuracy(done)
+    print(f"[bench] batched FP32/mixed densities against the FP64 solves: {acc}", file=sys.stderr, flush=True)
+    return dict(trace=desc, trace_is_full=full, batched=batched, one_at_a_time_fp64=fifo,
                 speedup_throughput=round(batched["throughput_req_s"] / fifo["throughput_req_s"], 3),
-                outcome_agreement=f"{agree}/{len(done)}")
+                outcome_agreement=f"{agree}/{len(done)}",
+                accuracy_vs_fp64=dict(metric="per-request relative max-norm error of rho_R, rho_B at the "
+                                             "final step, batched result against the FP64 solve", **acc))
 
 
 def copy_probe(n: int):

@@ -41,6 +41,7 @@ class Request:
     outcome: str = ""
     steps_done: int = 0
     info: dict = field(default_factory=dict)
+    final: tuple = None     # (rho_R, rho_B) device FP64 tensors at the end, when kept
 
 
 def sc_coexistence(G: float):
@@ -221,7 +222,7 @@ class Server:
     """
 
     def __init__(self, k_steps=100, use_graph=True, reserve_bytes=4 << 30, max_resident=512,
-                 log=None, policy="swf", max_nodes=32 << 20):
+                 log=None, policy="swf", max_nodes=32 << 20, keep_fields=False):
         import torch
         if policy not in ("shared", "swf"):
             raise ValueError(f"unknown policy {policy!r}")
@@ -233,6 +234,7 @@ class Server:
         self.max_nodes = max_nodes if policy == "swf" else None
         self.stream = torch.cuda.Stream()
         self.log = log or (lambda *a: None)
+        self.keep_fields = keep_fields   # keep each finished request's final densities (on the device)
 
     def free_bytes(self):
         import torch
@@ -305,6 +307,8 @@ class Server:
                     req.outcome = "done" if st[i] == M.DONE else "diverged"
                     if st[i] == M.DONE and sim.diverged():
                         req.outcome = "diverged"
+                    if self.keep_fields and req.outcome == "done":
+                        req.final = sim.moments()[:2]
                     done.append(req)
                     sim.close()
                     self.log(f"[serve] {req.rid} {req.outcome} after {req.steps_done} steps")
@@ -313,9 +317,21 @@ class Server:
         return done, now()
 
 
-def serve_one_at_a_time(trace, check_every=1000, log=None):
+def density_error(a, ref):
+    """Relative max-norm error of the densities a = (rho_R, rho_B) against
+    ref: max over the components present of max|a_k - ref_k| / max|ref_k|."""
+    err = 0.0
+    for x, r in zip(a, ref):
+        scale = float(np.abs(r).max())
+        if scale > 0.0:
+            err = max(err, float(np.abs(x - r).max()) / scale)
+    return err
+
+
+def serve_one_at_a_time(trace, check_every=1000, log=None, keep_fields=False):
     """Reference: FIFO, one simulation at a time, FP64, two-pass kernels, no
-    graphs; a request cannot start before it arrives."""
+    graphs; a request cannot start before it arrives.  keep_fields: keep each
+    finished request's final densities on the device (req.final)."""
     import torch
     import paper_2110_05197_amd as M
     log = log or (lambda *a: None)
@@ -335,10 +351,43 @@ def serve_one_at_a_time(trace, check_every=1000, log=None):
         req.steps_done = done
         req.finished = now()
         req.outcome = "diverged" if st == M.DIVERGED else "done"
+        if keep_fields and req.outcome == "done":
+            req.final = sim.moments()[:2]
         sim.close()
         out.append(req)
         log(f"[fifo] {req.rid} {req.outcome}")
     return out, now()
+
+
+def compare_runs(served, reference):
+    """Per-request density error of `served` against `reference` (two runs
+    of one trace that kept their final fields): sets info["rho_err"] on the
+    served requests that finished on both sides and releases the fields."""
+    ref = {r.rid: r for r in reference}
+    for r in served:
+        q = ref.get(r.rid)
+        if r.final is not None and q is not None and q.final is not None:
+            a = tuple(t.cpu().numpy() for t in r.final)
+            b = tuple(t.cpu().numpy() for t in q.final)
+            r.info["rho_err"] = density_error(a, b)
+    for r in list(served) + list(reference):
+        r.final = None
+
+
+def accuracy(reqs):
+    """Max and 99th percentile of the per-request density errors (info
+    "rho_err"), overall and per storage precision."""
+    import paper_2110_05197_amd as M
+    names = {M.FP32: "fp32", M.MIXED: "mixed", M.FP16: "fp16", M.FP64: "fp64"}
+    out = {}
+    groups = {"all": [r for r in reqs if "rho_err" in r.info]}
+    for r in groups["all"]:
+        groups.setdefault(names.get(r.params["precision"], "other"), []).append(r)
+    for key, rs in groups.items():
+        e = np.array([r.info["rho_err"] for r in rs])
+        out[key] = dict(requests=len(rs), max=float(e.max()) if len(e) else None,
+                        p99=float(np.percentile(e, 99)) if len(e) else None)
+    return out
 
 
 def summarize(reqs, wall):
