@@ -26,8 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D3Q19 CG MLUPS + % HBM roofline at 256^3; sweep-serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# what the fused step's machine code is made from: its sources and the build flags
-KERNEL_SOURCES = ["csrc/node.hpp", "csrc/kernels.hpp", "csrc/fused.hpp", "csrc/lattice.hpp", "_build.py"]
+# what the fused step's machine code and its memory layout are made from: its sources, the
+# library source that lays out the population arrays, and the build flags
+KERNEL_SOURCES = ["csrc/node.hpp", "csrc/kernels.hpp", "csrc/fused.hpp", "csrc/lattice.hpp", "csrc/mclbm.hip",
+                  "_build.py"]
 
 
 def kernel_hash() -> str:
@@ -126,23 +128,48 @@ def stream_probe(n: int):
             sys.exit(r.returncode)
 
 
-def cpu_baseline(rR, rB, n: int, steps: int):
-    """The FP64 oracle (as it stands, OpenMP over the host cores) on `steps`
-    steps of the same fields."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu prints it)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rR, rB, n: int, steps: int, steps_one_thread: int):
+    """The FP64 oracle (as it stands: one pass per step over plain arrays,
+    OpenMP over the host cores) on `steps` steps of the same fields, built
+    here with -O3 -march=native, then on one thread for `steps_one_thread`
+    steps.  Each timing includes the oracle's per-call scratch allocation."""
+    import tempfile
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
-    oracle.build(force=False)
+    tmp = tempfile.mkdtemp(prefix="mclbm_oracle_")
+    oracle.use_library(oracle.build_timing(tmp))
     p = oracle.make_params(lattice=1, model=0, nx=n, ny=n, nz=n, rho0_R=1.0, rho0_B=1.0,
                            tau_R=1.0, tau_B=1.0, A=0.005, beta=0.7)
-    f = oracle.init_equilibrium(p, rR, rB)
+    f0 = oracle.init_equilibrium(p, rR, rB)
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
-    f = oracle.run(p, f, steps)
+    f = oracle.run(p, f0, steps)
     dt = time.perf_counter() - t0
     del f
-    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"FP64 oracle, D3Q19 CG {n}^3 of the same 32-droplet fields, {steps} steps "
-                       f"({dt:.1f} s wall)")
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    f = oracle.run(p, f0, steps_one_thread)
+    dt1 = time.perf_counter() - t0
+    del f, f0
+    oracle.set_threads(threads)
+    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"FP64 oracle, D3Q19 CG {n}^3 of the same 32-droplet fields, {steps} steps on "
+                       f"{threads} threads ({dt:.1f} s wall)",
+                one_thread=dict(value=n ** 3 * steps_one_thread / dt1 / 1e6, unit="MLUPS",
+                                steps=steps_one_thread, wall_s=round(dt1, 1)),
+                cpu_model=cpu_model(), build="gcc -O3 -march=native -fopenmp -ffp-contract=off")
 
 
 def serving_leg(full: bool):
@@ -162,25 +189,33 @@ def serving_leg(full: bool):
     print(f"[bench] serving: {desc}", file=sys.stderr, flush=True)
     # the full trace runs for minutes: report each finished request
     log = (lambda s: print(s, file=sys.stderr, flush=True)) if full else None
-    trace = serve.make_trace(seed=0, **kw)
-    server = serve.Server(k_steps=100, log=log, keep_fields=True)
-    done, wall = server.run(trace)
-    batched = serve.summarize(done, wall)
-    print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+    runs = {}
+    for rule in ("fp64", "gamma"):
+        trace = serve.make_trace(seed=0, precision_rule=rule, **kw)
+        done, wall = serve.Server(k_steps=100, log=log, keep_fields=True).run(trace)
+        runs[rule] = (done, serve.summarize(done, wall))
+        print(f"[bench] batched ({rule} rule): {runs[rule][1]}", file=sys.stderr, flush=True)
     trace2 = serve.make_trace(seed=0, **kw)
     done2, wall2 = serve.serve_one_at_a_time(trace2, log=log, keep_fields=True)
     fifo = serve.summarize(done2, wall2)
     print(f"[bench] one-at-a-time FP64: {fifo}", file=sys.stderr, flush=True)
-    agree = sum(1 for a, b in zip(sorted(done, key=lambda r: r.rid), sorted(done2, key=lambda r: r.rid))
-                if a.outcome == b.outcome)
-    serve.compare_runs(done, done2)
-    acc = serve.accuracy(done)
-    print(f"[bench] batched FP32/mixed densities against the FP64 solves: {acc}", file=sys.stderr, flush=True)
-    return dict(trace=desc, trace_is_full=full, batched=batched, one_at_a_time_fp64=fifo,
-                speedup_throughput=round(batched["throughput_req_s"] / fifo["throughput_req_s"], 3),
-                outcome_agreement=f"{agree}/{len(done)}",
-                accuracy_vs_fp64=dict(metric="per-request relative max-norm error of rho_R, rho_B at the "
-                                             "final step, batched result against the FP64 solve", **acc))
+    by2 = {r.rid: r for r in done2}
+    out = dict(trace=desc, trace_is_full=full, one_at_a_time_fp64=fifo,
+               accuracy_metrics="per request, batched result against its FP64 solve at the final step: "
+                                "rho_err = relative max-norm error of rho_R and rho_B; volume_err, jump_err = "
+                                "relative difference of the red volume and of the density jump rho_in - rho_out "
+                                "across the interface; ekin_ratio_max = largest kinetic-energy ratio")
+    for rule, key in (("gamma", "batched_fp32_mixed"), ("fp64", "batched")):
+        done, summ = runs[rule]
+        serve.compare_runs(done, done2, release_reference=(rule == "fp64"))
+        agree = sum(1 for r in done if by2.get(r.rid) is not None and by2[r.rid].outcome == r.outcome)
+        acc = serve.accuracy(done)
+        print(f"[bench] {key} against the FP64 solves: {acc}", file=sys.stderr, flush=True)
+        out[key] = dict(precision=("FP32 below density ratio 100, FP64 from 100" if rule == "fp64"
+                                   else "FP32 below density ratio 100, mixed from 100"),
+                        **summ, speedup_throughput=round(summ["throughput_req_s"] / fifo["throughput_req_s"], 3),
+                        outcome_agreement=f"{agree}/{len(done)}", accuracy_vs_fp64=acc)
+    return out
 
 
 def copy_probe(n: int):
@@ -216,6 +251,7 @@ def main():
     ap.add_argument("--precision", type=int, default=1, help="0 FP64, 1 FP32, 2 mixed, 3 FP16")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto (fused), 1 two-pass, 2 fused")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps-one-thread", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the sweep-serving leg")
     ap.add_argument("--serve-full", action="store_true",
@@ -230,7 +266,7 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=100_000)
     ap.add_argument("--model", default="CG", choices=sorted(MODELS))
     ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
-    ap.add_argument("--study", choices=["rp", "ligament", "oscillation", "contraction", "dropOsc"],
+    ap.add_argument("--study", choices=["rp", "ligament", "oscillation", "contraction", "dropOsc", "drift"],
                     help="physics run of a paper case instead of the benchmark: the Rayleigh-Plateau jet "
                          "(CG and SC, breakup and satellites), the density-ratio-1000 ligament "
                          "(mixed and FP16 storage), the 128^3 oscillating droplet (FP32 and FP64) or the "
@@ -248,7 +284,14 @@ def main():
         import paper_2110_05197_amd as M
         from paper_2110_05197_amd import studies
         log = lambda *a: print(*a, file=sys.stderr, flush=True)
-        if args.study == "rp":
+        if args.study == "drift":
+            n = args.size
+            rR, rB = workload_fields(n, 0, args.model, args.lattice)
+            out = dict(study="mass-drift", workload=f"{args.lattice} {args.model} {n}^3 periodic, 32 seeded droplets",
+                       precision=args.precision,
+                       run=studies.mass_drift(M, params(n, args.precision, args.kernel, args.model, args.lattice),
+                                              rR, rB, steps=args.study_steps or 10000, log=log))
+        elif args.study == "rp":
             steps = args.study_steps or 30000
             sc = studies.sc_mc_sigma(M)
             log(f"[rp] Shan-Chen sigma {sc['sigma']:.4f} (Laplace, R = {sc['radius']:.2f})")
@@ -321,7 +364,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and headline:
         print(f"[bench] cpu baseline ({args.cpu_steps} oracle steps)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(rR, rB, n, args.cpu_steps)
+        cpu = cpu_baseline(rR, rB, n, args.cpu_steps, args.cpu_steps_one_thread)
 
     serving = None
     if not args.no_serve:

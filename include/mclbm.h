@@ -214,9 +214,9 @@ mclbm_status mclbm_init_equilibrium(mclbm_sim *sim, const double *d_rhoR, const 
                                     const double *d_u);
 
 /* Advance nsteps time steps.  check_every > 0: every check_every steps (and
- * at the end) read the device divergence flag (synchronises) and stop early
- * with MCLBM_DIVERGED if it is set; check_every == 0: fully asynchronous, no
- * early exit.  *steps_done (may be NULL) receives the steps taken.
+ * at the end) check the current state as mclbm_diverged does (synchronises)
+ * and stop early with MCLBM_DIVERGED if it is bad or a step saw a bad state;
+ * check_every == 0: fully asynchronous, no early exit.  *steps_done (may be NULL) receives the steps taken.
  * With check_every == 0 the call only enqueues kernel launches on the sim's
  * stream (no copy, fill or synchronisation), so a caller may capture it into
  * a HIP graph.  The ping-pong buffer index and the step counter advance on
@@ -249,7 +249,10 @@ mclbm_status mclbm_checkpoint_bytes(const mclbm_sim *sim, size_t *bytes);
 mclbm_status mclbm_checkpoint(mclbm_sim *sim, void *d_dst, int64_t *step);
 mclbm_status mclbm_restore(mclbm_sim *sim, const void *d_src, int64_t step);
 
-/* Read the device divergence flag (synchronises): 1 if set. */
+/* 1 if the current state has a node with a non-finite moment or rho <= 0,
+ * or any earlier state since the last init / import / restore had one (a
+ * step flags the state it reads; this call also scans the current one,
+ * one read of the populations).  Synchronises. */
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged);
 
 /* Interface observables.  The phase indicator of a node is rho^N =
@@ -350,10 +353,14 @@ mclbm_status mclbm_batch_kernels(const mclbm_batch *b, int32_t *kernels);
 mclbm_status mclbm_batch_step(mclbm_batch *b, int32_t ksteps, int32_t use_graph);
 
 /* Status words and steps taken per sim (host arrays of n; synchronises).
- * Also updates each sim's own step counter. */
+ * Also updates each sim's own step counter and current buffer.  The state a
+ * sim that reached its target ends in is scanned once (one read of its
+ * populations) and reported MCLBM_STOPPED_DIVERGED if it is bad: the steps
+ * themselves flag only the states they read. */
 mclbm_status mclbm_batch_status(mclbm_batch *b, int32_t *status, int64_t *steps);
 
-/* Release the batch (the sims stay valid; synchronises). */
+/* Release the batch (synchronises).  The sims stay valid and receive their
+ * step counters and current buffers, as from mclbm_batch_status. */
 mclbm_status mclbm_batch_destroy(mclbm_batch *b);
 
 #ifdef __cplusplus

@@ -54,14 +54,35 @@ DEFAULTS = dict(lattice=1, model=0, nx=8, ny=8, nz=8, bc=(0, 0, 0), enhanced_eq=
                 Pi=0.0, chi=1.0, Ga_R=0.0, Ga_B=0.0, Gr_R=0.0, Gr_B=0.0)
 
 _lib = None
+_lib_path = None   # None: the parity build; else a timing build (use_library)
+
+
+def build_timing(directory: str) -> str:
+    """The same source built for timing on the host that runs it (gcc -O3
+    -march=native, OpenMP; contraction off as in the parity build) into
+    `directory`; the benchmark's CPU baseline times this copy."""
+    path = os.path.join(directory, "libmclbm_oracle_timing.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-ffp-contract=off", "-std=c11",
+                           "-shared", "-fPIC", "-o", path, _SRC, "-lm"])
+    return path
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from `path` (a build_timing copy) from now on."""
+    global _lib, _lib_path
+    _lib = None
+    _lib_path = path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = _lib_path
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(Params)
         L.orc_lattice_tables.argtypes = [ctypes.c_int, ctypes.c_double,

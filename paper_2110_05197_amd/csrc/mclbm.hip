@@ -488,6 +488,9 @@ struct mclbm_batch {
     std::vector<mclbm_sim *> sims;
     std::vector<int> order;          // descriptor slot -> index into sims
     std::vector<int64_t> step0;
+    // per descriptor slot: the final state of a sim that reached its target
+    // has been scanned for divergence (and was found diverged)
+    std::vector<char> final_scanned, final_bad;
     hipStream_t stream;
     SimDesc *d_desc;
     SimDesc *h_desc;
@@ -734,6 +737,10 @@ mclbm_status mclbm_fused_tile(const mclbm_sim *sim, int32_t *tx, int32_t *ty, in
 mclbm_status mclbm_diverged(mclbm_sim *sim, int32_t *diverged)
 {
     if (!sim || !diverged) return fail(MCLBM_EINVAL, "NULL argument");
+    // a step flags the state it reads; scan the state the last step wrote
+    sim->ops->density(sim->kp, sim->f[sim->cur], sim->field, sim->d_flag, sim->stream);
+    mclbm_status s = launched("diverged");
+    if (s) return s;
     MCLBM_HIP(hipMemcpyAsync(sim->h_flag, sim->d_flag, sizeof(unsigned), hipMemcpyDeviceToHost, sim->stream));
     MCLBM_HIP(hipStreamSynchronize(sim->stream));
     *diverged = *sim->h_flag ? 1 : 0;
@@ -878,9 +885,13 @@ mclbm_status mclbm_restore(mclbm_sim *sim, const void *d_src, int64_t step)
 // --------------------------------------------------------------------------
 // Batches.
 // --------------------------------------------------------------------------
+static mclbm_status batch_sync_sims(mclbm_batch *b, int32_t *status, int64_t *steps);
+
 mclbm_status mclbm_batch_destroy(mclbm_batch *b)
 {
     if (!b) return MCLBM_OK;
+    // hand each sim its step count and current buffer, as mclbm_batch_status does
+    if (b->d_desc && b->h_desc && !b->order.empty()) (void)batch_sync_sims(b, nullptr, nullptr);
     (void)hipStreamSynchronize(b->stream);
     for (hipStream_t s : b->side) (void)hipStreamSynchronize(s);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -985,6 +996,8 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
             d.state = target_steps[idx] > 0 ? MCLBM_RUNNING : MCLBM_DONE;
             b->order.push_back(idx);
             b->step0.push_back(s->step);
+            b->final_scanned.push_back(0);
+            b->final_bad.push_back(0);
             ++slot;
         }
         b->groups.push_back(g);
@@ -1086,22 +1099,53 @@ mclbm_status mclbm_batch_kernels(const mclbm_batch *b, int32_t *kernels)
 mclbm_status mclbm_batch_status(mclbm_batch *b, int32_t *status, int64_t *steps)
 {
     if (!b) return fail(MCLBM_EINVAL, "batch is NULL");
+    return batch_sync_sims(b, status, steps);
+}
+
+}  // extern "C"
+
+// Descriptor state back to the sims (current buffer, step count) and to the
+// caller.  A step flags the state it reads, so the state the last step of a
+// sim that reached its target wrote is scanned here, once: a bad final state
+// turns DONE into STOPPED_DIVERGED (and sets the sim's divergence flag).
+static mclbm_status batch_sync_sims(mclbm_batch *b, int32_t *status, int64_t *steps)
+{
     const int n = (int)b->sims.size();
     MCLBM_HIP(hipMemcpyAsync(b->h_desc, b->d_desc, sizeof(SimDesc) * n, hipMemcpyDeviceToHost, b->stream));
     MCLBM_HIP(hipStreamSynchronize(b->stream));
+    std::vector<int> scan;
+    for (int slot = 0; slot < n; ++slot) {
+        const SimDesc &d = b->h_desc[slot];
+        if (d.state == MCLBM_DONE && !b->final_scanned[slot]) {
+            mclbm_sim *s = b->sims[b->order[slot]];
+            s->ops->density(s->kp, s->f[d.cur], s->field, s->d_flag, b->stream);
+            scan.push_back(slot);
+        }
+    }
+    for (int slot : scan) {
+        mclbm_sim *s = b->sims[b->order[slot]];
+        MCLBM_HIP(hipMemcpyAsync(s->h_flag, s->d_flag, sizeof(unsigned), hipMemcpyDeviceToHost, b->stream));
+    }
+    if (!scan.empty()) {
+        mclbm_status st = launched("batch_status");
+        if (st) return st;
+        MCLBM_HIP(hipStreamSynchronize(b->stream));
+    }
+    for (int slot : scan) {
+        b->final_scanned[slot] = 1;
+        b->final_bad[slot] = *b->sims[b->order[slot]]->h_flag ? 1 : 0;
+    }
     for (int slot = 0; slot < n; ++slot) {
         const int idx = b->order[slot];
         const SimDesc &d = b->h_desc[slot];
         mclbm_sim *s = b->sims[idx];
         s->cur = d.cur;
         s->step = b->step0[slot] + d.steps;
-        if (status) status[idx] = d.state;
+        if (status) status[idx] = (d.state == MCLBM_DONE && b->final_bad[slot]) ? MCLBM_STOPPED_DIVERGED : d.state;
         if (steps) steps[idx] = d.steps;
     }
     return MCLBM_OK;
 }
-
-}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // Interface observables

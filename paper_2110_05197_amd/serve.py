@@ -42,6 +42,7 @@ class Request:
     steps_done: int = 0
     info: dict = field(default_factory=dict)
     final: tuple = None     # (rho_R, rho_B) device FP64 tensors at the end, when kept
+    obs: dict = None        # observables at the end, when kept
 
 
 def sc_coexistence(G: float):
@@ -131,16 +132,18 @@ def sc_coupling_for_ratio(gamma: float) -> float:
 
 def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 512),
                d3_sizes=(64, 80, 96, 112, 128, 144, 160), steps_range=(1000, 20000),
-               precisions=(1, 2), precision_rule="gamma"):
+               precisions=(1, 2), precision_rule="fp64"):
     """Seeded request trace: Poisson arrivals at `rate` per second; model CG
     or SC (p = 1/2); droplet (R = L/4) or ligament (R = L/8, aspect 5, capped
     to 0.8 L); D2Q9 or D3Q19 (p = 1/2) with L from the size lists; density
     ratio 10^U(0,3), viscosity ratio 10^U(0,2), sigma 10^U(-3,-1); steps
-    U{steps_range}; FP32 or mixed storage.  precision_rule "gamma": FP32 below
-    density ratio 100 and mixed from 100 on (the light-phase FP64 arithmetic
-    of the mixed path is what high density ratios need); "random": drawn from
-    `precisions`.  The draw is made under both rules, so the traces differ
-    in precision only."""
+    U{steps_range}.  Storage precision, precision_rule "fp64": FP32 below
+    density ratio 100 and FP64 from 100 on (FP32 and mixed storage carry the
+    heavy colour's rounding into the light phase at high density ratios: its
+    density and the spurious currents drift away from the FP64 solution over
+    thousands of steps); "gamma": FP32 below 100 and mixed from 100 on;
+    "random": drawn from `precisions`.  The draw is made under every rule,
+    so the traces differ in precision only."""
     import paper_2110_05197_amd as M
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -156,7 +159,9 @@ def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 5
         sigma = 10 ** rng.uniform(-3, -1)
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
         prec = int(rng.choice(precisions))
-        if precision_rule == "gamma":
+        if precision_rule == "fp64":
+            prec = M.FP64 if gamma >= 100.0 else M.FP32
+        elif precision_rule == "gamma":
             prec = M.MIXED if gamma >= 100.0 else M.FP32
         elif precision_rule != "random":
             raise ValueError(f"unknown precision rule {precision_rule!r}")
@@ -309,6 +314,7 @@ class Server:
                         req.outcome = "diverged"
                     if self.keep_fields and req.outcome == "done":
                         req.final = sim.moments()[:2]
+                        req.obs = sim.observables()
                     done.append(req)
                     sim.close()
                     self.log(f"[serve] {req.rid} {req.outcome} after {req.steps_done} steps")
@@ -353,16 +359,29 @@ def serve_one_at_a_time(trace, check_every=1000, log=None, keep_fields=False):
         req.outcome = "diverged" if st == M.DIVERGED else "done"
         if keep_fields and req.outcome == "done":
             req.final = sim.moments()[:2]
+            req.obs = sim.observables()
         sim.close()
         out.append(req)
         log(f"[fifo] {req.rid} {req.outcome}")
     return out, now()
 
 
-def compare_runs(served, reference):
-    """Per-request density error of `served` against `reference` (two runs
-    of one trace that kept their final fields): sets info["rho_err"] on the
-    served requests that finished on both sides and releases the fields."""
+def _rel(a, b):
+    return abs(a - b) / abs(b) if b != 0 else (0.0 if a == b else math.inf)
+
+
+def compare_runs(served, reference, release_reference=True):
+    """Per-request differences of `served` from `reference` (two runs of one
+    trace that kept their final fields and observables), set in the served
+    requests' info for those that finished on both sides:
+      rho_err    relative max-norm error of rho_R, rho_B (density_error);
+      volume_err relative difference of the red (liquid) volume;
+      jump_err   relative difference of the density jump rho_in - rho_out
+                 across the interface (the Laplace test's measure);
+      ekin_ratio kinetic energy (spurious currents of a resting drop) over the
+                 reference's.
+    The served fields are released afterwards, and the reference's unless
+    release_reference is false (to compare a second run against it)."""
     ref = {r.rid: r for r in reference}
     for r in served:
         q = ref.get(r.rid)
@@ -370,13 +389,19 @@ def compare_runs(served, reference):
             a = tuple(t.cpu().numpy() for t in r.final)
             b = tuple(t.cpu().numpy() for t in q.final)
             r.info["rho_err"] = density_error(a, b)
-    for r in list(served) + list(reference):
+            if r.obs is not None and q.obs is not None:
+                o, p = r.obs, q.obs
+                r.info["volume_err"] = _rel(o["red_volume"], p["red_volume"])
+                r.info["jump_err"] = _rel(o["rho_in"] - o["rho_out"], p["rho_in"] - p["rho_out"])
+                r.info["ekin_ratio"] = o["ekin"] / p["ekin"] if p["ekin"] > 0 else math.nan
+    for r in list(served) + (list(reference) if release_reference else []):
         r.final = None
 
 
 def accuracy(reqs):
-    """Max and 99th percentile of the per-request density errors (info
-    "rho_err"), overall and per storage precision."""
+    """Per storage precision (and over all): the number of compared requests,
+    max and 99th percentile of rho_err, volume_err and jump_err, and the
+    largest kinetic-energy ratio (see compare_runs)."""
     import paper_2110_05197_amd as M
     names = {M.FP32: "fp32", M.MIXED: "mixed", M.FP16: "fp16", M.FP64: "fp64"}
     out = {}
@@ -384,9 +409,13 @@ def accuracy(reqs):
     for r in groups["all"]:
         groups.setdefault(names.get(r.params["precision"], "other"), []).append(r)
     for key, rs in groups.items():
-        e = np.array([r.info["rho_err"] for r in rs])
-        out[key] = dict(requests=len(rs), max=float(e.max()) if len(e) else None,
-                        p99=float(np.percentile(e, 99)) if len(e) else None)
+        g = dict(requests=len(rs))
+        for name in ("rho_err", "volume_err", "jump_err"):
+            e = np.array([r.info[name] for r in rs if name in r.info and math.isfinite(r.info[name])])
+            g[name] = dict(max=float(e.max()), p99=float(np.percentile(e, 99))) if len(e) else None
+        k = np.array([r.info["ekin_ratio"] for r in rs if math.isfinite(r.info.get("ekin_ratio", math.nan))])
+        g["ekin_ratio_max"] = float(k.max()) if len(k) else None
+        out[key] = g
     return out
 
 

@@ -26,6 +26,11 @@ reporting the quantities the paper measures on them.
   crossings along z near the axis, the retraction speed of each end against
   the capillary speed sqrt(sigma / (rho_R R0)) of the contraction section,
   the droplet count and divergence.
+* ``mass_drift(params, fields)``: how each colour's total mass moves under
+  reduced-precision storage (exact in FP64) over many steps, sampled every
+  ``every`` steps, with the exponent b of |drift| ~ t^b fitted over the later
+  samples (b = 1: a bias that accumulates at a steady rate; b = 1/2: a random
+  walk of the per-step rounding) and how often the drift keeps its sign.
 """
 from __future__ import annotations
 
@@ -503,3 +508,36 @@ def oscillation_table(M, radii=OSC_RADII, models=("CG", "SC"), cg_sigmas=(0.05,)
         for R in radii:
             rows.append(oscillation_run(M, "CG", float(R), beta=b, log=log))
     return rows
+
+
+def mass_drift(M, params: dict, rR, rB, steps: int = 10000, every: int = 250, log=print):
+    """Relative change of each colour's total mass every `every` steps over
+    `steps` steps of one lattice, and its growth law (see the module notes)."""
+    sim = M.Sim(params)
+    sim.init_equilibrium(rR, rB)
+    o0 = sim.observables()
+    ts, dR, dB = [], [], []
+    t0 = time.perf_counter()
+    for s in range(every, steps + 1, every):
+        st, _ = sim.step(every, check_every=every)
+        if st != M.OK:
+            break
+        o = sim.observables()
+        ts.append(s)
+        dR.append((o["mass_R"] - o0["mass_R"]) / o0["mass_R"])
+        dB.append((o["mass_B"] - o0["mass_B"]) / o0["mass_B"])
+        if s % (every * 8) == 0:
+            log(f"[drift] step {s}: red {dR[-1]:+.3e}, blue {dB[-1]:+.3e}")
+    wall = time.perf_counter() - t0
+    sim.close()
+    t = np.array(ts, dtype=float)
+
+    def law(d):
+        d = np.array(d)
+        late = (t >= t[-1] / 10) & (np.abs(d) > 0)
+        b = float(np.polyfit(np.log(t[late]), np.log(np.abs(d[late])), 1)[0]) if late.sum() >= 3 else float("nan")
+        same = float(np.mean(np.sign(d[late]) == np.sign(d[-1]))) if late.any() else float("nan")
+        return dict(final=float(d[-1]), per_step=float(d[-1] / t[-1]), exponent=b, same_sign_fraction=same)
+
+    return dict(steps=int(t[-1]) if len(t) else 0, every=every, wall_s=round(wall, 1),
+                red=law(dR), blue=law(dB), series=dict(step=ts, red=dR, blue=dB))

@@ -30,6 +30,11 @@ def M():
     return M
 
 
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def rel_err(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
@@ -419,9 +424,58 @@ def test_divergence_is_detected(M):
     f = s.export_f()
     f[0, 3, 2, 2, 2] = float("nan")
     s.import_f(f)
+    assert s.diverged()           # the check scans the current state itself
+    s.import_f(f)
     st, done = s.step(50, check_every=10)
     assert st == M.DIVERGED and done == 10
     assert s.observables()["diverged"] == 1.0
+
+
+def test_batch_reports_a_bad_final_state(M):
+    """A sim whose last state is bad (here: imported with a NaN and given no
+    steps to take) is reported STOPPED_DIVERGED by the batch status, not
+    DONE, while a healthy one is DONE; a sim that diverges while stepping
+    stops early."""
+    shape = (8, 8, 64)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=64, ny=8, nz=8, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 25)
+    sims = []
+    for bad in (True, False, True):
+        s = M.Sim(p)
+        s.init_equilibrium(rR, rB, u)
+        if bad:
+            f = s.export_f()
+            f[1, 5, 3, 3, 3] = float("nan")
+            s.import_f(f)
+        sims.append(s)
+    b = M.Batch(sims, [0, 12, 12])
+    b.step(4, use_graph=False)
+    st, steps = b.status()
+    assert st[0] == M.STOPPED_DIVERGED and steps[0] == 0
+    assert st[2] == M.STOPPED_DIVERGED and steps[2] < 12
+    b.step(10, use_graph=False)
+    st, steps = b.status()
+    assert st == [M.STOPPED_DIVERGED, M.DONE, M.STOPPED_DIVERGED] and steps[1] == 12
+    b.close()
+
+
+def test_batch_close_hands_back_steps_and_state(M):
+    """Closing a stepped batch without asking its status leaves each sim
+    with the right step count and current buffer: the sim then equals the
+    same steps taken alone."""
+    shape = (16, 16, 64)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=64, ny=16, nz=16, A=0.02)
+    rR, rB, u = cg_droplet_case(shape, 26)
+    _, solo = gpu_run(M, p, rR, rB, u, 13)
+    s = M.Sim(p)
+    s.init_equilibrium(rR, rB, u)
+    b = M.Batch([s], [13])
+    b.step(5, use_graph=False)
+    b.step(10, use_graph=False)
+    torch_sync()
+    b.close()
+    assert s.observables()["step"] == 13
+    assert np.array_equal(s.export_f().cpu().numpy(), solo)
 
 
 def test_import_export_round_trip(M):
