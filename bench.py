@@ -40,10 +40,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name: str, per_launch_units: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_fused_cg_d3q19_fp32_256.md")
+TRAFFIC_PROFILES = {"D3Q19": "traffic_fused_cg_d3q19_fp32_256.md",
+                    "D2Q9": "traffic_fused_cg_d2q9_fp32_4096.md"}
+
+
+def measured_traffic(lattice: str):
+    """HBM bytes per launch of the one-pass CG FP32 step on the lattice's
+    benchmark workload, from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILES[lattice])
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -264,6 +269,8 @@ def main():
                     help="only run a static-droplet study of the paper (Laplace error, or CG vs SC "
                          "spurious-current energy over sigma) as one GPU batch")
     ap.add_argument("--sweep-steps", type=int, default=100_000)
+    ap.add_argument("--sweep-serve", action="store_true",
+                    help="run the Laplace sweep's droplets as requests of the sweep server")
     ap.add_argument("--model", default="CG", choices=sorted(MODELS))
     ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D2Q9"])
     ap.add_argument("--study", choices=["rp", "ligament", "oscillation", "contraction", "dropOsc", "drift"],
@@ -314,7 +321,7 @@ def main():
         return
     if args.sweep:
         from paper_2110_05197_amd import sweeps
-        out = sweeps.run(args.sweep, steps=args.sweep_steps,
+        out = sweeps.run(args.sweep, steps=args.sweep_steps, via_server=args.sweep_serve,
                          log=lambda *a: print(*a, file=sys.stderr, flush=True))
         print(json.dumps(_finite(out)))
         return
@@ -330,7 +337,9 @@ def main():
         sys.exit(1)
     n = args.size
     headline = args.model == "CG" and args.lattice == "D3Q19"
-    print(f"[bench] generating {args.lattice} {args.model} fields ({n}^3 nodes)", file=sys.stderr, flush=True)
+    print(f"[bench] generating {args.lattice} {args.model} fields ({n}^3 = "
+          f"{'x'.join(str(d) for d in shape_of(n, args.lattice)[::-1] if d > 1)} nodes)",
+          file=sys.stderr, flush=True)
     rR, rB = workload_fields(n, 0, args.model, args.lattice)
     p = params(n, args.precision, args.kernel, args.model, args.lattice)
     sim = M.Sim(p)
@@ -357,7 +366,8 @@ def main():
     drift = abs(o1["mass_R"] - o0["mass_R"]) / o0["mass_R"] if o0["mass_R"] else 0.0
     print(f"[bench] {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, "
           f"mass drift {drift:.2e}, diverged={o1['diverged']}", file=sys.stderr, flush=True)
-    traffic = measured_traffic("k_fused", N) if (fused and headline and args.precision == 1 and n == 256) else None
+    traffic = (measured_traffic(args.lattice)
+               if (fused and args.model == "CG" and args.precision == 1 and n == 256) else None)
     del sim
     torch.cuda.empty_cache()
 

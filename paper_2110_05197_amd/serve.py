@@ -35,6 +35,7 @@ class Request:
     gamma: float
     nu_ratio: float
     sigma: float
+    radius: float = None    # droplet radius (default L/4)
     # filled in by the server
     admitted: float = math.nan
     finished: float = math.nan
@@ -192,7 +193,7 @@ def initial_fields(req: Request):
     else:
         rhoL, rhoG = p["rho0_R"], p["rho0_B"]
     if req.case == "droplet":
-        rR, rB = inputs.droplet(shape, L / 4.0, rhoL, rhoG)
+        rR, rB = inputs.droplet(shape, req.radius if req.radius else L / 4.0, rhoL, rhoG)
     else:
         R = L / 8.0
         rR, rB = inputs.ligament(shape, R, min(10 * R, 0.8 * L), rhoL, rhoG, axis=0)
@@ -394,14 +395,23 @@ def compare_runs(served, reference, release_reference=True):
                 r.info["volume_err"] = _rel(o["red_volume"], p["red_volume"])
                 r.info["jump_err"] = _rel(o["rho_in"] - o["rho_out"], p["rho_in"] - p["rho_out"])
                 r.info["ekin_ratio"] = o["ekin"] / p["ekin"] if p["ekin"] > 0 else math.nan
+                r.info["ekin"], r.info["ekin_ref"] = o["ekin"], p["ekin"]
     for r in list(served) + (list(reference) if release_reference else []):
         r.final = None
+
+
+def _describe(r):
+    return dict(rid=r.rid, model="CG" if r.params["model"] == 0 else "SC",
+                lattice="D3Q19" if r.params["nz"] > 1 else "D2Q9", L=r.params["nx"],
+                case=r.case, gamma=round(r.gamma, 2), nu_ratio=round(r.nu_ratio, 2),
+                sigma=float(f"{r.sigma:.3g}"), steps=r.steps)
 
 
 def accuracy(reqs):
     """Per storage precision (and over all): the number of compared requests,
     max and 99th percentile of rho_err, volume_err and jump_err, and the
-    largest kinetic-energy ratio (see compare_runs)."""
+    largest kinetic-energy ratio (see compare_runs), each maximum with the
+    request it came from (worst)."""
     import paper_2110_05197_amd as M
     names = {M.FP32: "fp32", M.MIXED: "mixed", M.FP16: "fp16", M.FP64: "fp64"}
     out = {}
@@ -410,11 +420,19 @@ def accuracy(reqs):
         groups.setdefault(names.get(r.params["precision"], "other"), []).append(r)
     for key, rs in groups.items():
         g = dict(requests=len(rs))
+        worst = {}
         for name in ("rho_err", "volume_err", "jump_err"):
-            e = np.array([r.info[name] for r in rs if name in r.info and math.isfinite(r.info[name])])
+            fin = [r for r in rs if name in r.info and math.isfinite(r.info[name])]
+            e = np.array([r.info[name] for r in fin])
             g[name] = dict(max=float(e.max()), p99=float(np.percentile(e, 99))) if len(e) else None
-        k = np.array([r.info["ekin_ratio"] for r in rs if math.isfinite(r.info.get("ekin_ratio", math.nan))])
-        g["ekin_ratio_max"] = float(k.max()) if len(k) else None
+            if fin:
+                worst[name] = _describe(max(fin, key=lambda r: r.info[name]))
+        fin = [r for r in rs if math.isfinite(r.info.get("ekin_ratio", math.nan))]
+        g["ekin_ratio_max"] = max(r.info["ekin_ratio"] for r in fin) if fin else None
+        if fin:
+            w = max(fin, key=lambda r: r.info["ekin_ratio"])
+            worst["ekin_ratio"] = dict(_describe(w), ekin=w.info["ekin"], ekin_ref=w.info["ekin_ref"])
+        g["worst"] = worst
         out[key] = g
     return out
 

@@ -169,8 +169,30 @@ def _batch_run(M, params, fields, steps, chunk, log, label, record_every=None):
     return out + (history,) if record_every else out
 
 
-def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=print):
-    """Run one study as a batch; returns the per-case results and the fits."""
+def _served_run(M, todo, params, steps, chunk, log):
+    """The members as requests of the continuous-batching server (all
+    arriving at once); returns their final observables, steps and outcomes
+    in `todo` order, and the wall time."""
+    from . import serve
+    reqs = [serve.Request(i, 0.0, p, "droplet", steps, g, r, SIGMA, radius=float(R))
+            for i, ((R, g, r), p) in enumerate(zip(todo, params))]
+    server = serve.Server(k_steps=min(chunk, steps), keep_fields=True, policy="shared",
+                          log=lambda s: None)
+    done, wall = server.run(reqs)
+    by = {q.rid: q for q in done}
+    out = []
+    for i in range(len(todo)):
+        q = by[i]
+        q.final = None
+        out.append((q.obs, q.steps_done, q.outcome, q))
+    log(f"[sweep] served {len(todo)} members in {wall:.1f} s")
+    return out, wall
+
+
+def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=print, via_server: bool = False):
+    """Run one study as a batch (or, via_server, as requests of the sweep
+    server, which takes the same steps bit for bit); returns the per-case
+    results and the fits."""
     import paper_2110_05197_amd as M
     if study == "ekin":
         return run_ekin(steps=steps, chunk=chunk, log=log)
@@ -183,14 +205,24 @@ def run(study: str, steps: int = 100_000, radii=RADII, chunk: int = 500, log=pri
         L = p["nx"]
         params.append(p)
         fields.append(inputs.droplet((L, L, L), float(R), p["rho0_R"], p["rho0_B"]))
-    sims, st, counts, wall = _batch_run(M, params, fields, steps, chunk, log, study)
     results = []
-    for (R, g, r), s, p, stat, n in zip(todo, sims, params, st, counts):
-        o = s.observables()
-        m = measure(o, p, R0=R)
-        m.update(R0=R, gamma=g, nu_ratio=r, steps=int(n), diverged=bool(o["diverged"] or stat == M.STOPPED_DIVERGED))
-        results.append(m)
-        s.close()
+    if via_server:
+        served, wall = _served_run(M, todo, params, steps, chunk, log)
+        counts = [n for (_, n, _, _) in served]
+        for (R, g, r), p, (o, n, outcome, _) in zip(todo, params, served):
+            m = measure(o, p, R0=R) if o is not None else dict(R=float("nan"), sigma_cal=float("nan"),
+                                                               E=float("nan"), ekin_per_area=float("nan"))
+            m.update(R0=R, gamma=g, nu_ratio=r, steps=int(n), diverged=outcome != "done")
+            results.append(m)
+    else:
+        sims, st, counts, wall = _batch_run(M, params, fields, steps, chunk, log, study)
+        for (R, g, r), s, p, stat, n in zip(todo, sims, params, st, counts):
+            o = s.observables()
+            m = measure(o, p, R0=R)
+            m.update(R0=R, gamma=g, nu_ratio=r, steps=int(n),
+                     diverged=bool(o["diverged"] or stat == M.STOPPED_DIVERGED))
+            results.append(m)
+            s.close()
     key = "gamma" if study == "density" else "nu_ratio"
     fits = {}
     for v in sorted({m[key] for m in results}):

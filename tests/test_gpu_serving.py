@@ -122,6 +122,44 @@ def test_laplace_sweep_machinery(M):
     assert e[12] < e[8], e
 
 
+def test_laplace_sweep_served(M, orc):
+    """The Laplace study's droplets as requests of the sweep server: the same
+    results, bit for bit, as the batched sweep (R = 8, 12 at density ratios 1
+    in FP32 and 100 in FP64, 64^3, 1000 steps), and one served FP64 member
+    (R = 12, density ratio 100) element by element against the oracle's
+    1000 steps of the same droplet (relative max norm of rho_R, rho_B within
+    1e-10)."""
+    from paper_2110_05197_amd import serve, sweeps
+    orig = sweeps.cases
+    try:
+        sweeps.cases = lambda study, radii=(8, 12): [(R, g, 1.0) for g in (1, 100) for R in radii]
+        a = sweeps.run("density", steps=1000, radii=(8, 12), chunk=250, log=lambda *x: None)
+        b = sweeps.run("density", steps=1000, radii=(8, 12), chunk=250, log=lambda *x: None, via_server=True)
+    finally:
+        sweeps.cases = orig
+    assert len(a["results"]) == len(b["results"]) == 4
+    for ma, mb in zip(a["results"], b["results"]):
+        for k in ("sigma_cal", "R", "R_equimolar", "E", "ekin_per_area", "steps", "diverged"):
+            assert ma[k] == mb[k], (k, ma, mb)
+    # one member against the oracle
+    p = sweeps.case_params(M, 12, 100, 1.0)
+    assert p["precision"] == M.FP64
+    L = p["nx"]
+    reqs = [serve.Request(0, 0.0, p, "droplet", 1000, 100.0, 1.0, sweeps.SIGMA, radius=12.0),
+            serve.Request(1, 0.0, sweeps.case_params(M, 8, 1, 1.0), "droplet", 700, 1.0, 1.0, sweeps.SIGMA,
+                          radius=8.0)]
+    done, _ = serve.Server(k_steps=100, keep_fields=True, policy="shared").run(reqs)
+    served = {r.rid: r for r in done}[0]
+    assert served.outcome == "done" and served.steps_done == 1000
+    rR, rB = serve.initial_fields(reqs[0])
+    fo = orc.run(p, orc.init_equilibrium(p, rR, rB, None), 1000)
+    ro_R, ro_B, _ = orc.moments(p, fo)
+    g = tuple(t.cpu().numpy() for t in served.final)
+    err = serve.density_error(g, (ro_R, ro_B))
+    print("served FP64 member against the oracle:", err, flush=True)
+    assert err <= 1e-10
+
+
 def test_ekin_sweep_machinery(M):
     """The CG-vs-SC stationary-droplet study (sweeps.run_ekin) on a reduced
     case, R = 20 in 64^3, 4000 steps: SC at two couplings, CG at two sigmas

@@ -67,15 +67,23 @@ def test_trace_is_seeded():
 
 
 def test_trace_precision_rule():
-    """Rule "gamma": mixed storage exactly for density ratios >= 100; the
-    rest of the trace is the one the "random" rule draws."""
+    """Rule "fp64" (the default): FP64 storage exactly for density ratios >=
+    100, FP32 below; rule "gamma": mixed storage there instead; the rest of
+    the trace is the one the "random" rule draws."""
     import paper_2110_05197_amd as M
-    g = serve.make_trace(seed=5, n=60)
+    d = serve.make_trace(seed=5, n=60)
+    g = serve.make_trace(seed=5, n=60, precision_rule="gamma")
     r = serve.make_trace(seed=5, n=60, precision_rule="random")
+    assert any(x.gamma >= 100 for x in d) and any(x.gamma < 100 for x in d)
+    assert all(x.params["precision"] == (M.FP64 if x.gamma >= 100 else M.FP32) for x in d)
     assert all(x.params["precision"] == (M.MIXED if x.gamma >= 100 else M.FP32) for x in g)
     assert {x.params["precision"] for x in r} == {M.FP32, M.MIXED}
     strip = lambda d: {k: v for k, v in d.items() if k != "precision"}
-    assert all(strip(a.params) == strip(b.params) and a.arrival == b.arrival for a, b in zip(g, r))
+    for t in (d, g):
+        assert all(strip(a.params) == strip(b.params) and a.arrival == b.arrival
+                   for a, b in zip(t, r))
+    with pytest.raises(ValueError):
+        serve.make_trace(seed=5, n=4, precision_rule="fp16")
 
 
 def test_initial_fields_sc_at_coexistence():
@@ -102,3 +110,26 @@ def test_summarize_percentiles():
     assert s["requests"] == 10 and s["throughput_req_s"] == 0.5
     assert s["p50_latency_s"] == pytest.approx(5.5) and s["p99_latency_s"] == pytest.approx(9.91)
     assert s["glups"] == pytest.approx(10 * 100 * 100 / 20 / 1e9, abs=1e-3)
+
+
+def test_accuracy_summary_names_the_worst_requests():
+    """accuracy(): counts, maxima and the request each maximum came from, per
+    storage precision and over all; requests without a comparison are left
+    out, a non-finite ratio does not become the maximum."""
+    import paper_2110_05197_amd as M
+    tr = serve.make_trace(seed=1, n=6, precision_rule="random")
+    errs = [1e-5, 3e-4, 2e-5, 7e-6, 5e-5, None]
+    for r, e in zip(tr, errs):
+        r.params["precision"] = M.FP32 if r.rid % 2 == 0 else M.MIXED
+        if e is not None:
+            r.info.update(rho_err=e, volume_err=e / 10, jump_err=e / 100,
+                          ekin_ratio=math.nan if r.rid == 1 else 1 + 10 * e,
+                          ekin=1.0, ekin_ref=1.0)
+    acc = serve.accuracy(tr)
+    assert acc["all"]["requests"] == 5
+    assert acc["all"]["rho_err"]["max"] == 3e-4 and acc["all"]["worst"]["rho_err"]["rid"] == 1
+    assert acc["all"]["worst"]["ekin_ratio"]["rid"] == 4      # rid 1 has a nan ratio
+    fp32 = [r for r in tr if r.params["precision"] == M.FP32 and "rho_err" in r.info]
+    assert acc["fp32"]["requests"] == len(fp32)
+    assert acc["fp32"]["rho_err"]["max"] == max(r.info["rho_err"] for r in fp32)
+    assert acc["mixed"]["worst"]["volume_err"]["rid"] == 1
