@@ -30,11 +30,13 @@
 //   *-ldsK           : the same kernel with K KB of (unused) dynamic LDS per
 //                      block, capping the blocks a compute unit holds at once
 //   copy-float4-gs   : float4 copy by 2048 blocks looping over the array
-//   march-*-TXxTY    : the one-pass step's schedule without its stencil and
+//   march-*-TXxTY-cC : the one-pass step's schedule without its stencil and
 //                      arithmetic: each block owns a TX x TY column and walks
-//                      its half of the planes (two chunks in z), loading plane
-//                      z+1 while storing plane z, aligned or pushed (c_x = 0
-//                      stores non-temporal); periodic wrap at the faces
+//                      one of C equal runs of planes (C chunks in z; C sets the
+//                      blocks per compute unit), loading plane z+1 while
+//                      storing plane z, aligned or pushed (c_x = 0 stores
+//                      non-temporal); periodic wrap at the faces.  march-tiled
+//                      stores each column's plane contiguously (a tiled layout)
 // Population arrays are `stride` = n^3 + pad floats apart (pad from the command
 // line, a multiple of 64): with pad = 0 and n a power of two every array
 // starts at the same offset modulo a large power of two.  Nodes are kept one
@@ -251,45 +253,56 @@ __global__ __launch_bounds__(256) void copy4_gs(const float4 *__restrict__ a, fl
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = a[i];
 }
 
-// z-march of a TX x TY column over planes [z0, z0 + n/2): the one-pass step's
-// schedule with its loads and stores only.
-template <int TX, int TY, bool PUSH>
+// z-march of a TX x TY column over one of `chunks` equal runs of planes: the
+// one-pass step's schedule with its loads and stores only.  TILED stores the
+// nodes tile by tile (each TX x TY column's plane one contiguous run of TX*TY
+// values per array) instead of row by row.
+template <int TX, int TY, bool TILED>
+__device__ __forceinline__ unsigned march_index(int x, int y, int z, int n)
+{
+    if (!TILED) return (unsigned)(x + n * (y + n * z));
+    const int tiles_x = n / TX, tiles_y = n / TY;
+    return (unsigned)(((z * tiles_y + y / TY) * tiles_x + x / TX) * (TX * TY) + (y % TY) * TX + x % TX);
+}
+
+template <int TX, int TY, bool PUSH, bool TILED = false>
 __global__ __launch_bounds__(TX *TY) void march(const float *__restrict__ src, float *__restrict__ dst, int n,
-                                                long long S)
+                                                long long S, int chunks)
 {
     const int tiles_x = n / TX, tiles_y = n / TY;
     const int nb = (int)gridDim.x;
     const int t = nb % 8 ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (nb / 8) + (int)blockIdx.x / 8;
     const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
     const int x = bx * TX + (int)threadIdx.x % TX, y = by * TY + (int)threadIdx.x / TX;
-    const int z0 = bz * (n / 2), z1 = z0 + n / 2;
-    const int sxy = n * n, N = n * n * n;
+    const int z0 = bz * (n / chunks), z1 = z0 + n / chunks;
     float c[2 * Q], d[2 * Q];
     auto ld = [&](int z, float (&v)[2 * Q]) {
-        const unsigned o = (unsigned)(x + n * (y + n * z));
+        const unsigned o = march_index<TX, TY, TILED>(x, y, z, n);
 #pragma unroll
         for (int i = 0; i < 2 * Q; ++i) v[i] = (src + (size_t)i * (size_t)S)[o];
     };
     ld(z0, c);
     for (int z = z0; z < z1; ++z) {
         if (z + 1 < z1) ld(z + 1, d);
-        const int nn = x + n * (y + n * z);
-        const int dxp = x == n - 1 ? 1 - n : 1, dxm = x == 0 ? n - 1 : -1;
-        const int dyp = y == n - 1 ? n - sxy : n, dym = y == 0 ? sxy - n : -n;
-        const int dzp = z == n - 1 ? sxy - N : sxy, dzm = z == 0 ? N - sxy : -sxy;
+        const int xp = x == n - 1 ? 0 : x + 1, xm = x == 0 ? n - 1 : x - 1;
+        const int yp = y == n - 1 ? 0 : y + 1, ym = y == 0 ? n - 1 : y - 1;
+        const int zp = z == n - 1 ? 0 : z + 1, zm = z == 0 ? n - 1 : z - 1;
         float s = 0.f;
 #pragma unroll
         for (int i = 0; i < 2 * Q; ++i) s += c[i];
 #pragma unroll
         for (int i = 0; i < 2 * Q; ++i) {
             const int q = i % Q;
-            int dd = 0;
+            unsigned o;
             if (PUSH) {
-                if (CX[q]) dd += CX[q] > 0 ? dxp : dxm;
-                if (CY[q]) dd += CY[q] > 0 ? dyp : dym;
-                if (CZ[q]) dd += CZ[q] > 0 ? dzp : dzm;
+                const int tx = CX[q] > 0 ? xp : CX[q] < 0 ? xm : x;
+                const int ty = CY[q] > 0 ? yp : CY[q] < 0 ? ym : y;
+                const int tz = CZ[q] > 0 ? zp : CZ[q] < 0 ? zm : z;
+                o = march_index<TX, TY, TILED>(tx, ty, tz, n);
+            } else {
+                o = march_index<TX, TY, TILED>(x, y, z, n);
             }
-            float *p = &(dst + (size_t)i * (size_t)S)[(unsigned)(nn + dd)];
+            float *p = &(dst + (size_t)i * (size_t)S)[o];
             const float w = scale(c[i], s);
             if (!PUSH || CX[q] == 0) __builtin_nontemporal_store(w, p);
             else *p = w;
@@ -467,25 +480,40 @@ int main(int argc, char **argv)
     }
     {
         const dim3 b512(512);
-        auto mgrid = [&](int tx, int ty) { return dim3((unsigned)((nx / tx) * (nx / ty) * 2)); };
-        run("march-aligned-64x8", [&](float *x, float *y) {
-            hipLaunchKernelGGL((march<64, 8, false>), mgrid(64, 8), b512, 0, 0, x, y, nx, S);
-        });
-        run("march-push-64x8", [&](float *x, float *y) {
-            hipLaunchKernelGGL((march<64, 8, true>), mgrid(64, 8), b512, 0, 0, x, y, nx, S);
-        });
-        run("march-aligned-128x4", [&](float *x, float *y) {
-            hipLaunchKernelGGL((march<128, 4, false>), mgrid(128, 4), b512, 0, 0, x, y, nx, S);
-        });
-        run("march-push-128x4", [&](float *x, float *y) {
-            hipLaunchKernelGGL((march<128, 4, true>), mgrid(128, 4), b512, 0, 0, x, y, nx, S);
-        });
-        if (nx % 256 == 0) {
-            run("march-aligned-256x2", [&](float *x, float *y) {
-                hipLaunchKernelGGL((march<256, 2, false>), mgrid(256, 2), b512, 0, 0, x, y, nx, S);
+        auto mgrid = [&](int tx, int ty, int ch) { return dim3((unsigned)((nx / tx) * (nx / ty) * ch)); };
+        char name[64];
+        for (int ch : {2, 4, 8}) {
+            std::snprintf(name, sizeof name, "march-aligned-64x8-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<64, 8, false>), mgrid(64, 8, ch), b512, 0, 0, x, y, nx, S, ch);
             });
-            run("march-push-256x2", [&](float *x, float *y) {
-                hipLaunchKernelGGL((march<256, 2, true>), mgrid(256, 2), b512, 0, 0, x, y, nx, S);
+            std::snprintf(name, sizeof name, "march-push-64x8-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<64, 8, true>), mgrid(64, 8, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+            std::snprintf(name, sizeof name, "march-tiled-aligned-64x8-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<64, 8, false, true>), mgrid(64, 8, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+            std::snprintf(name, sizeof name, "march-tiled-push-64x8-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<64, 8, true, true>), mgrid(64, 8, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+            std::snprintf(name, sizeof name, "march-aligned-128x4-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<128, 4, false>), mgrid(128, 4, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+            std::snprintf(name, sizeof name, "march-push-128x4-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<128, 4, true>), mgrid(128, 4, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+        }
+        if (nx % 256 == 0) {
+            run("march-aligned-256x2-c2", [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<256, 2, false>), mgrid(256, 2, 2), b512, 0, 0, x, y, nx, S, 2);
+            });
+            run("march-push-256x2-c2", [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<256, 2, true>), mgrid(256, 2, 2), b512, 0, 0, x, y, nx, S, 2);
             });
         }
     }
