@@ -292,24 +292,29 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
 }
 
 // Batched one-pass step: the blocks of all eligible simulations of a group
-// (D3Q19, nx a multiple of 64, ny of the column height) in one launch per
-// boundary kind; a block finds its simulation in the descriptor array
-// (one-pass block ranges), skips it unless it is running and of the launch's
-// kind (all faces periodic, or not), and processes one column of that
-// simulation.  The per-node arithmetic is the solo kernels', so a batched
+// (D3Q19, ny a multiple of the column height) in one launch per kind; a
+// block finds its simulation in the descriptor array (one-pass block ranges),
+// skips it unless it is running and of the launch's kind (all faces periodic
+// or not; nx a multiple of 64 or not), and processes one column of that
+// simulation.  EDGE launches take the simulations whose nx is not a multiple
+// of 64 and run every column through the masked column body (the last column
+// in x holds nx mod 64 nodes; a full column computes the same as unmasked).  The per-node arithmetic is the solo kernels', so a batched
 // simulation evolves bitwise as it would alone.  Columns: 64-wide rows (at 16
 // or 32 nodes the rows of the x-shifted pushes split cache lines between
 // neighbouring blocks and the step runs at half speed), 8 rows (4 in FP64 and
 // in mixed precision, whose FP64 sums need the registers).  One kernel per
-// boundary kind keeps a single column body per kernel: with both inlined the
+// kind keeps a single column body per kernel: with two inlined the
 // mixed-precision kernel needed 270 registers (one wave per SIMD) and ran no
-// faster than the batched two-pass kernels.  No masked edge columns here (the
-// batched two-pass kernels were as fast on the ragged sizes measured, 96^3 and
-// 160^3).
+// faster than the batched two-pass kernels.
 constexpr int kBatchTX = 64;
 constexpr int batch_ty(int precision) { return precision == 0 || precision == 2 ? 4 : 8; }
-// which kernels a group launches: bit 0 all-periodic sims, bit 1 others
-constexpr int kFusedPeriodic = 1, kFusedBounded = 2;
+// which kernels a group launches: all-periodic sims and others, each with nx
+// a multiple of 64 or not (EDGE)
+constexpr int kFusedPeriodic = 1, kFusedBounded = 2, kFusedPeriodicEdge = 4, kFusedBoundedEdge = 8;
+constexpr int fused_kind(bool periodic, bool edge)
+{
+    return edge ? (periodic ? kFusedPeriodicEdge : kFusedBoundedEdge) : (periodic ? kFusedPeriodic : kFusedBounded);
+}
 
 __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long b)
 {
@@ -321,7 +326,7 @@ __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long
     return lo;
 }
 
-template <int PR, int MODEL, bool PERIODIC>
+template <int PR, int MODEL, bool PERIODIC, bool EDGE>
 __global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, int nsims)
 {
     constexpr int kBatchTY = batch_ty(PR);
@@ -330,15 +335,16 @@ __global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, i
     const SimDesc &d = D[s];
     if (d.state != 0) return;
     if ((d.P.bc[0] == 0 && d.P.bc[1] == 0 && d.P.bc[2] == 0) != PERIODIC) return;
+    if ((d.P.nx % kBatchTX != 0) != EDGE) return;
     const long long b = blockIdx.x - d.fblock0;
-    const int tiles_x = d.P.nx / kBatchTX, tiles_y = d.P.ny / kBatchTY;
+    const int tiles_x = (d.P.nx + kBatchTX - 1) / kBatchTX, tiles_y = d.P.ny / kBatchTY;
     const int bx = (int)(b % tiles_x), by = (int)((b / tiles_x) % tiles_y), bz = (int)(b / ((long long)tiles_x * tiles_y));
     const int x0 = bx * kBatchTX, y0 = by * kBatchTY, z0 = bz * d.ftz, z1 = min(z0 + d.ftz, d.P.nz);
     using S = typename Prec<PR>::S;
     const S *src = global_ptr<const S>(d.f[d.cur]);
     S *dst = global_ptr<S>(d.f[d.cur ^ 1]);
     unsigned *flag = global_ptr<unsigned>(d.flag);
-    fused_column<PR, MODEL, kBatchTX, kBatchTY, PERIODIC>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
+    fused_column<PR, MODEL, kBatchTX, kBatchTY, PERIODIC, EDGE>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
 // Planes per column of the batched simulations of a group.  A column
@@ -377,8 +383,8 @@ inline int batch_group_tz(const long long *cols, const int *nz, int n, long long
     return best;
 }
 
-// Blocks of kb_fused<PR, MODEL, *> the device holds at once (the smaller of
-// the two boundary kinds).
+// Blocks of kb_fused<PR, MODEL, *, *> the device holds at once (the smallest
+// over the four kinds).
 template <int PR, int MODEL>
 long long batch_fused_resident()
 {
@@ -387,7 +393,8 @@ long long batch_fused_resident()
     if (hipGetDevice(&dev) != hipSuccess
         || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 256;
-    const void *fns[2] = {(const void *)kb_fused<PR, MODEL, true>, (const void *)kb_fused<PR, MODEL, false>};
+    const void *fns[4] = {(const void *)kb_fused<PR, MODEL, true, false>, (const void *)kb_fused<PR, MODEL, false, false>,
+                          (const void *)kb_fused<PR, MODEL, true, true>, (const void *)kb_fused<PR, MODEL, false, true>};
     for (const void *fn : fns) {
         int b = 0;
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -398,25 +405,23 @@ long long batch_fused_resident()
     return (long long)std::max(1, per_cu) * std::max(1, cus);
 }
 
-// kinds: kFusedPeriodic and/or kFusedBounded, the boundary kinds present.
+// kinds: the fused_kind() bits of the simulations present.
 template <int PR, int MODEL>
 void launch_batch_fused(SimDesc *D, int n, long long fblocks, int kinds, hipStream_t s)
 {
     constexpr int lds = fused_lds_bytes<PR, MODEL, kBatchTX, batch_ty(PR)>();
+    const void *fns[4] = {(const void *)kb_fused<PR, MODEL, true, false>, (const void *)kb_fused<PR, MODEL, false, false>,
+                          (const void *)kb_fused<PR, MODEL, true, true>, (const void *)kb_fused<PR, MODEL, false, true>};
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  lds);
-        (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  lds);
+        for (const void *fn : fns) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
-    if (kinds & kFusedPeriodic)
-        hipLaunchKernelGGL((kb_fused<PR, MODEL, true>), dim3((unsigned)fblocks), dim3(kBatchTX * batch_ty(PR)), lds,
-                           s, D, n);
-    if (kinds & kFusedBounded)
-        hipLaunchKernelGGL((kb_fused<PR, MODEL, false>), dim3((unsigned)fblocks), dim3(kBatchTX * batch_ty(PR)), lds,
-                           s, D, n);
+    const dim3 grid((unsigned)fblocks), block(kBatchTX * batch_ty(PR));
+    if (kinds & kFusedPeriodic) hipLaunchKernelGGL((kb_fused<PR, MODEL, true, false>), grid, block, lds, s, D, n);
+    if (kinds & kFusedBounded) hipLaunchKernelGGL((kb_fused<PR, MODEL, false, false>), grid, block, lds, s, D, n);
+    if (kinds & kFusedPeriodicEdge) hipLaunchKernelGGL((kb_fused<PR, MODEL, true, true>), grid, block, lds, s, D, n);
+    if (kinds & kFusedBoundedEdge) hipLaunchKernelGGL((kb_fused<PR, MODEL, false, true>), grid, block, lds, s, D, n);
 }
 
 struct FusedShape {

@@ -131,14 +131,19 @@ bool auto_prefers_fused(const mclbm_params &p)
     return p.lattice != MCLBM_D2Q9 || (long long)p.nx * p.ny >= (1LL << 19);
 }
 
-// The batched one-pass kernel takes 64 x batch_ty columns; a sim whose
-// kernel is pinned to the two-pass path keeps it.
+// The batched one-pass kernel takes 64 x batch_ty columns, the last one in x
+// masked when 64 does not divide nx, as long as at least three quarters of
+// the columns' lanes hold nodes (measured against the batched two-pass
+// kernels, FP32: nx = 112 1.17x, 96 and 48 1.05-1.08x, 144 and 160 1.01-1.06x;
+// nx = 80 0.95x, 32 0.92x); a sim whose kernel is pinned to the two-pass path
+// keeps it.
 // `resident`: the group's Ops::batch_fused_resident() (0: no batched
 // one-pass kernel for this lattice, model and precision).
 bool batch_fused_ok(const mclbm_params &p, long long resident)
 {
-    return resident > 0 && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS && p.nx % kBatchTX == 0
-           && p.ny % batch_ty(p.precision) == 0;
+    const long long lanes = (long long)kBatchTX * ((p.nx + kBatchTX - 1) / kBatchTX);
+    return resident > 0 && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS
+           && p.ny % batch_ty(p.precision) == 0 && 4LL * p.nx >= 3 * lanes;
 }
 
 mclbm_status validate(const mclbm_params *p)
@@ -498,7 +503,7 @@ struct mclbm_batch {
         const Ops *ops;
         int first, count;
         long long blocks, fblocks, oblocks;
-        int fused_kinds;   // kFusedPeriodic | kFusedBounded: boundary kinds of its one-pass sims
+        int fused_kinds;   // fused_kind() bits of its one-pass sims
         bool any_outflow;
     };
     std::vector<Group> groups;
@@ -954,7 +959,7 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         for (int idx : groups[key]) {
             const mclbm_params &q = sims[idx]->prm;
             if (batch_fused_ok(q, resident)) {
-                fcols.push_back((long long)(q.nx / kBatchTX) * (q.ny / batch_ty(q.precision)));
+                fcols.push_back((long long)((q.nx + kBatchTX - 1) / kBatchTX) * (q.ny / batch_ty(q.precision)));
                 fnz.push_back(q.nz);
             }
         }
@@ -975,12 +980,12 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
             d.fblock0 = g.fblocks;
             if (batch_fused_ok(s->prm, resident)) {
                 d.ftz = batch_fused_tz(s->prm.nz, group_tz);
-                d.fnblocks = (long long)(s->prm.nx / kBatchTX) * (s->prm.ny / batch_ty(s->prm.precision))
-                             * ((s->prm.nz + d.ftz - 1) / d.ftz);
+                d.fnblocks = (long long)((s->prm.nx + kBatchTX - 1) / kBatchTX)
+                             * (s->prm.ny / batch_ty(s->prm.precision)) * ((s->prm.nz + d.ftz - 1) / d.ftz);
                 g.fblocks += d.fnblocks;
                 const bool periodic = s->prm.bc[0] == MCLBM_PERIODIC && s->prm.bc[1] == MCLBM_PERIODIC
                                       && s->prm.bc[2] == MCLBM_PERIODIC;
-                g.fused_kinds |= periodic ? kFusedPeriodic : kFusedBounded;
+                g.fused_kinds |= fused_kind(periodic, s->prm.nx % kBatchTX != 0);
             } else {
                 d.nblocks = grid_of(s->kp.N);
                 g.blocks += d.nblocks;
