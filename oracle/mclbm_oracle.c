@@ -23,14 +23,17 @@
  * Readings of passages where the paper is silent or garbled carry the tag
  * "reading:" and are listed, with their reasons, in the design notes.
  *
- * Every colour-gradient and Shan-Chen multiphase function here is pinned by a
- * CPU test against something other than this file (printed constants, moment
- * identities, closed-form decay rates including the blended viscosity of
- * Eq. interpVisc, the Laplace law, coexistence densities, invariants).  Parity
- * unpinned beyond invariants: the two-component Shan-Chen step's blend of
- * per-component relaxation times with one barycentric velocity (its cross force
- * is pinned by the demixing threshold), the physical magnitude of the CG
- * repulsion force, and the multirange Shan-Chen couplings' surface tension.
+ * Every function here is pinned by a CPU test against something other than
+ * this file: printed constants, moment identities, closed-form decay rates
+ * (including the blended viscosity of Eq. interpVisc), the Laplace law,
+ * coexistence densities, the two-component Shan-Chen step's exact relaxation
+ * of uniform component momenta and its one-step response to a sinusoidal
+ * density, the repulsion force's closed form on planar films, exact
+ * multirange forces on quadratic pseudopotentials, invariants.  What no pin
+ * can fix is physical calibration the paper leaves open: the repulsion
+ * magnitude and range (Pi and chi are free parameters), and the surface
+ * tension of the printed multirange couplings, which do not phase-separate
+ * under the printed equations.
  */
 #include <math.h>
 #include <stdint.h>

@@ -541,8 +541,9 @@ def test_sc_multiphase_conservation(orc):
 
 
 # --------------------------------------------------------------------------
-# Shan-Chen two-component (cross force only) -- parity unpinned beyond these
-# invariants.
+# Shan-Chen two-component (cross force only): invariants, the demixing
+# threshold, and closed forms of reading R20 (one barycentric velocity, each
+# component with its own relaxation time and Guo source).
 # --------------------------------------------------------------------------
 def test_sc_two_component_invariants(orc):
     shape = (8, 10, 12)
@@ -564,6 +565,109 @@ def test_sc_two_component_invariants(orc):
     assert np.allclose(orc.run(p, f2, 10), f2, atol=1e-15, rtol=0)
 
 
+def _component_momenta(orc, lattice, f):
+    c = orc.lattice_tables(lattice, 0.2)["c"].astype(float)
+    return np.einsum("kizyx,ia->kazyx", f, c)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_sc_two_component_barycentric_relaxation(orc, lattice):
+    """Reading R20 in a state where it has a closed form: uniform densities
+    (so the cross force sum_i w_i rho(x + c_i) c_i vanishes and streaming
+    leaves the state as it is) with each component moving at its own uniform
+    velocity.  Each step relaxes component s towards the equilibrium at the
+    one barycentric velocity u = (j_R + j_B)/rho with its own rate 1/tau_s,
+    whose first moment is rho_s u:  j_s <- j_s - (j_s - rho_s u)/tau_s.  With
+    tau_R != tau_B the total momentum changes by -sum_s (j_s - rho_s u)/tau_s
+    (a velocity weighted by 1/tau_s in the equilibria would conserve it, and
+    swapped relaxation times would change the rates: both fail here)."""
+    shape = (1, 4, 5) if lattice == 0 else (3, 4, 5)
+    tau = (0.7, 1.3)
+    rho = (0.8, 0.3)
+    vR, vB = np.array([0.02, -0.01, 0.005]), np.array([-0.03, 0.015, -0.004])
+    if lattice == 0:
+        vR[2] = vB[2] = 0.0
+    p = orc.make_params(lattice=lattice, model=2, nx=shape[2], ny=shape[1], nz=shape[0], G_RB=0.5,
+                        tau_R=tau[0], tau_B=tau[1])
+    ones = np.ones(shape)
+    uR = np.broadcast_to(vR[:, None, None, None], (3,) + shape).copy()
+    uB = np.broadcast_to(vB[:, None, None, None], (3,) + shape).copy()
+    f = orc.init_equilibrium(p, rho[0] * ones, 0.0 * ones, uR)
+    f[1] = orc.init_equilibrium(p, 0.0 * ones, rho[1] * ones, uB)[1]
+    j = [rho[0] * vR, rho[1] * vB]
+    for step in range(6):
+        f = orc.run(p, f, 1)
+        u = (j[0] + j[1]) / (rho[0] + rho[1])
+        j = [j[s] - (j[s] - rho[s] * u) / tau[s] for s in range(2)]
+        got = _component_momenta(orc, lattice, f)
+        for s in range(2):
+            for a in range(3):
+                assert np.allclose(got[s, a], j[s][a], rtol=0, atol=1e-15), (step, s, a)
+    moved = abs((j[0] + j[1]) - (rho[0] * vR + rho[1] * vB)).max()
+    assert moved > 1e-4          # the reading does not conserve total momentum here
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_sc_two_component_force_one_step(orc, lattice):
+    """The cross force of Eq. doublebeltrepulsionforce2 with Guo forcing, one
+    step from rest on rho_R = a (uniform), rho_B = b + eps sin(k x): on the
+    lattice, sum_i w_i sin(k c_ix) c_ix = sin(k)/3 and sum_i w_i c_ix^2
+    cos(k c_ix) = cos(k)/3 (both lattices), so to first order in eps
+      F_R = -(G/rho0^2) a eps sin(k)/3 cos(k x),  F_B = 0,
+      u = F_R / (2 rho)  (barycentric, with F/2),
+    the post-collision first moments are rho_s u / tau_s + (1 - 1/(2 tau_s)) F_s
+    (BGK and the Guo source's first moment), and streaming turns them and the
+    rest populations' pressure term into
+      j_x(x, 1) = [-eps sin(k)/3 + cos(k) (sum_s rho_s u0 / tau_s
+                                           + (1 - 1/(2 tau_R)) F0)] cos(k x)."""
+    nx = 24
+    shape = (1, 2, nx) if lattice == 0 else (2, 2, nx)
+    a, b, eps, G, r0 = 0.7, 0.4, 1e-6, 0.9, 1.1
+    tau = (0.8, 1.25)
+    p = orc.make_params(lattice=lattice, model=2, nx=nx, ny=shape[1], nz=shape[0], G_RB=G, rho0_X=r0,
+                        tau_R=tau[0], tau_B=tau[1])
+    x = np.arange(nx)
+    k = 2 * np.pi / nx
+    rR = np.full(shape, a)
+    rB = np.broadcast_to(b + eps * np.sin(k * x), shape).copy()
+    f1 = orc.run(p, orc.init_equilibrium(p, rR, rB), 1)
+    jx = _component_momenta(orc, lattice, f1).sum(axis=0)[0]
+    F0 = -(G / r0 ** 2) * a * eps * math.sin(k) / 3.0
+    u0 = F0 / (2.0 * (a + b))
+    amp = -eps * math.sin(k) / 3.0 + math.cos(k) * (a * u0 / tau[0] + b * u0 / tau[1]
+                                                  + (1.0 - 0.5 / tau[0]) * F0)
+    expect = amp * np.cos(k * x)
+    assert np.abs(jx - expect).max() < 1e-6 * abs(amp), (np.abs(jx - expect).max(), amp)
+    assert np.allclose(_component_momenta(orc, lattice, f1)[:, 1:], 0, atol=1e-20)
+
+
+@pytest.mark.parametrize("lattice,shape", [(0, (1, 64, 3)), (1, (3, 64, 3))])
+@pytest.mark.parametrize("case", ["equal_tau", "red_only", "blue_only"])
+def test_sc_two_component_shear_wave(orc, lattice, shape, case):
+    """Shear waves in the two-component Shan-Chen model with uniform
+    densities (no force): with tau_R = tau_B = 0.8 a 50/50 mixture decays at
+    the BGK viscosity (tau - 1/2)/3; with tau_R = 0.7, tau_B = 1.3 a
+    component alone decays at its own (tau_s - 1/2)/3."""
+    if case == "equal_tau":
+        tau, fr, nu = (0.8, 0.8), (0.5, 0.5), 0.1
+    elif case == "red_only":
+        tau, fr, nu = (0.7, 1.3), (1.0, 0.0), 0.2 / 3.0
+    else:
+        tau, fr, nu = (0.7, 1.3), (0.0, 1.0), 0.8 / 3.0
+    p = orc.make_params(lattice=lattice, model=2, nx=shape[2], ny=shape[1], nz=shape[0], G_RB=0.3,
+                        tau_R=tau[0], tau_B=tau[1])
+    u = inputs.shear_wave(shape, 1e-3, axis_u=0, axis_k=1)
+    f = orc.init_equilibrium(p, np.full(shape, fr[0]), np.full(shape, fr[1]), u)
+    steps = 300
+    rR, rB, j = orc.moments(p, orc.run(p, f, steps))
+    ux = j[0] / (rR + rB)
+    k = 2 * np.pi / shape[1]
+    prof = np.sin(k * np.arange(shape[1]))
+    amp = (ux.mean(axis=(0, 2)) * prof).sum() / (prof * prof).sum()
+    expect = math.exp(-nu * k * k * steps)
+    assert abs(amp / 1e-3 - expect) / expect < 0.01, (amp / 1e-3, expect)
+
+
 @pytest.mark.parametrize("G_RB,grows", [(0.7, False), (1.5, True)])
 def test_sc_two_component_demixing_threshold(orc, G_RB, grows):
     """Cross force F_s = -G rho_s grad rho_s' / 3 against the ideal pressure
@@ -580,8 +684,9 @@ def test_sc_two_component_demixing_threshold(orc, G_RB, grows):
 
 
 # --------------------------------------------------------------------------
-# CG repulsion force (Eq. repForce; reading psi_rep = (1 - |rho^N|)^chi) --
-# physics unpinned, properties only.
+# CG repulsion force (Eq. repForce; reading psi_rep = (1 - |rho^N|)^chi):
+# properties and the closed form on planar films.  Its calibration (Pi, chi)
+# is the paper's free choice.
 # --------------------------------------------------------------------------
 def test_repulsion_force_properties(orc):
     """Thin blue films across x separate red slabs: the force pushes the
@@ -609,6 +714,39 @@ def test_repulsion_force_properties(orc):
     assert abs(Fx[15]) < 0.1 * film and abs(Fx[16]) < 0.1 * film
     assert abs(Fx[15]) > 0                                    # defined, small, at the red max
     assert np.abs(Fx[2:5]).max() < 1e-12 * film               # no force where normals agree
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_repulsion_force_planar_closed_form(orc, lattice):
+    """Eq. repForce on films whose rho^N depends on x only: both normals are
+    +-x, the Heaviside factor is one exactly for the directions whose
+    neighbour lies across the extremum of rho^N (c_x = +1 from the node on
+    its left, -1 from the node on its right) and each such direction adds
+    2 c_x / |c_i|.  So the nodes beside an extremum feel
+        F_x = -+ Pi (1 - |rho^N|)^chi * 2 sum_{c_x = 1} 1/|c_i|
+    (2 + 2 sqrt 2 on D2Q9, 2 + 4 sqrt 2 on D3Q19; minus on the left: the
+    force points away from the extremum, reading R21), and every other node
+    none.  chi = 2 so that the exponent shows."""
+    nx, Pi, chi = 32, 0.01, 2.0
+    shape = (1, 3, nx) if lattice == 0 else (3, 3, nx)
+    x = np.arange(nx, dtype=float)
+    films = (7.5, 23.5)
+    dist = np.min([np.abs(x - c - nx * np.round((x - c) / nx)) for c in films], axis=0)
+    phi = np.tanh((dist - 2.5) / 2.0)
+    rR = np.broadcast_to(0.5 * (1 + phi), shape).copy()
+    rB = np.broadcast_to(0.5 * (1 - phi), shape).copy()
+    p = orc.make_params(lattice=lattice, nx=nx, ny=shape[1], nz=shape[0], Pi=Pi, chi=chi)
+    F = orc.repulsion_force(p, orc.init_equilibrium(p, rR, rB))
+    shell = 2.0 + (2.0 if lattice == 0 else 4.0) * math.sqrt(2.0)
+    expect = np.zeros(nx)
+    for left in (7, 15, 23, 31):      # extrema of rho^N at 7.5, 15.5, 23.5, 31.5
+        right = (left + 1) % nx
+        expect[left] = -Pi * (1.0 - abs(phi[left])) ** chi * shell
+        expect[right] = Pi * (1.0 - abs(phi[right])) ** chi * shell
+    for z in range(shape[0]):
+        for y in range(shape[1]):
+            assert np.allclose(F[0, z, y], expect, rtol=1e-12, atol=1e-18)
+    assert np.allclose(F[1:], 0.0, atol=1e-18)
 
 
 def test_repulsion_off_matches_plain_cg(orc):
