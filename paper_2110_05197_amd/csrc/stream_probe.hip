@@ -508,6 +508,17 @@ int main(int argc, char **argv)
                 hipLaunchKernelGGL((march<128, 4, true>), mgrid(128, 4, ch), b512, 0, 0, x, y, nx, S, ch);
             });
         }
+        for (int ch : {32, 64, 128}) {   // short runs of planes: 8, 4, 2 at n = 256
+            if (nx % ch) continue;
+            std::snprintf(name, sizeof name, "march-aligned-64x8-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<64, 8, false>), mgrid(64, 8, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+            std::snprintf(name, sizeof name, "march-push-64x8-c%d", ch);
+            run(name, [&](float *x, float *y) {
+                hipLaunchKernelGGL((march<64, 8, true>), mgrid(64, 8, ch), b512, 0, 0, x, y, nx, S, ch);
+            });
+        }
         if (nx % 256 == 0) {
             run("march-aligned-256x2-c2", [&](float *x, float *y) {
                 hipLaunchKernelGGL((march<256, 2, false>), mgrid(256, 2, 2), b512, 0, 0, x, y, nx, S, 2);
