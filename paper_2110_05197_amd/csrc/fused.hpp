@@ -298,8 +298,9 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
 // or not; nx a multiple of 64 or not), and processes one column of that
 // simulation.  EDGE launches take the simulations whose nx is not a multiple
 // of 64 and run every column through the masked column body (the last column
-// in x holds nx mod 64 nodes; a full column computes the same as unmasked).  The per-node arithmetic is the solo kernels', so a batched
-// simulation evolves bitwise as it would alone.  Columns: 64-wide rows (at 16
+// in x holds nx mod 64 nodes; a full column computes the same as unmasked).
+// The per-node arithmetic is the solo kernels', so a batched simulation
+// evolves bitwise as it would alone.  Columns: 64-wide rows (at 16
 // or 32 nodes the rows of the x-shifted pushes split cache lines between
 // neighbouring blocks and the step runs at half speed), 8 rows (4 in FP64 and
 // in mixed precision, whose FP64 sums need the registers).  One kernel per
