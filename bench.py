@@ -247,6 +247,72 @@ def _finite(x):
     return x
 
 
+# couplings of the droplet-collision study (Table dropcolParams, set 1), rho_0 = 0.83
+MULTIRANGE = dict(G_RB=0.405, Ga_R=-9.0, Ga_B=-8.0, Gr_R=8.1, Gr_B=7.1, psi_rho0=0.83, rho0_X=0.83,
+                  rho0_R=1.18, rho0_B=0.18, tau_R=1.0, tau_B=0.8)
+
+
+def next_rows(n: int, steps: int, reps: int = 20):
+    """The multirange Shan-Chen step and the interface observables on the n^3
+    workload: time per step or call, HIP events on the library's stream."""
+    import torch
+    import paper_2110_05197_amd as M
+    out = {}
+    rR, rB = workload_fields(n, 0)
+    frac = rR / (rR + rB)
+    N = n ** 3
+
+    def timed(fn, k):
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    # multirange two-component Shan-Chen (two-pass: the belts reach two nodes)
+    p = M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=M.FP32, nx=n, ny=n, nz=n, **MULTIRANGE)
+    sim = M.Sim(p)
+    sim.init_equilibrium(0.18 + frac, 0.18 + (1.0 - frac))
+    print(f"[bench] multirange step, {n}^3 FP32", file=sys.stderr, flush=True)
+    ms = timed(lambda: sim.step(1), steps)
+    o = sim.observables()
+    bpu = M.bytes_per_update(p)
+    # two-pass traffic: the density pass reads the populations and writes drho_R, drho_B, psi_R, psi_B
+    # (4 floats), the collide pass reads the populations and that field and writes the populations
+    moved = 1.5 * bpu + 2 * 4 * 4
+    out["multirange"] = dict(workload=f"SC two-component + multirange forces (Table dropcolParams set 1), {n}^3 periodic, "
+                                      "the bench droplets as species A (1.18 / 0.18)",
+                             kernel="two-pass (density + collide)", ms_per_step=round(ms, 4),
+                             mlups=round(N / (ms * 1e-3) / 1e6, 1), bytes_per_update=bpu,
+                             frac_algorithmic=round(bpu * N / (ms * 1e-3) / 8e12, 4),
+                             two_pass_bytes_per_update=moved,
+                             frac_two_pass_bytes=round(moved * N / (ms * 1e-3) / 8e12, 4),
+                             diverged=bool(o["diverged"]))
+    sim.close()
+    torch.cuda.empty_cache()
+    # interface observables on the CG bench state
+    p = params(n, 1)
+    sim = M.Sim(p)
+    sim.init_equilibrium(rR, rB)
+    sim.step(100)
+    print(f"[bench] interface observables on the {n}^3 CG state", file=sys.stderr, flush=True)
+    ms_x = timed(lambda: sim.interface_crossings(0, n // 2, n // 2), reps)
+    ms_a = timed(lambda: sim.plane_area(2, n // 2), reps)
+    ms_d = timed(lambda: sim.droplets(), 5)
+    nd = sim.droplets()
+    out["interface"] = dict(workload=f"CG bench state, {n}^3, after 100 steps",
+                            crossings_line_ms=round(ms_x, 4), plane_area_ms=round(ms_a, 4),
+                            droplets_ms=round(ms_d, 3), droplets_found=int(nd[0]) if isinstance(nd, tuple) else nd,
+                            droplets_nodes_per_s=round(N / (ms_d * 1e-3), 1))
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +327,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the sweep-serving leg")
     ap.add_argument("--serve-full", action="store_true",
                     help="serve the full 256-request trace (minutes) instead of the reduced one")
+    ap.add_argument("--next-rows", action="store_true",
+                    help="time the multirange Shan-Chen step and the interface observables on the workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one step's population bytes (counter calibration)")
     ap.add_argument("--stream-probe", action="store_true",
@@ -283,6 +351,9 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.size)
+        return
+    if args.next_rows:
+        print(json.dumps(next_rows(args.size, args.steps)))
         return
     if args.stream_probe:
         stream_probe(args.size)

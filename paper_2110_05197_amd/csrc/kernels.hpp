@@ -6,6 +6,7 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include <hip/hip_runtime.h>
 
@@ -228,35 +229,62 @@ __device__ __forceinline__ bool density_body(const KParams &P, const typename Pr
 //   F^a_s = -G^a_s psi_s(x) sum_{belt 1} w_i psi_s(x + c_i) c_i,
 //   F^r_s = -G^r_s psi_s(x) sum_{belts 1, 2} p_i psi_s(x + c_i) c_i,
 // from the psi fields of the density pass (field + 2N red, + 3N blue), the
-// sums taken over the pairs (c, -c) of the belt table.
-// (the belt table as device constant data: the pair loop stays rolled, so the
-// kernels that carry this branch keep the register budget of the plain model)
+// sums taken over the pairs (c, -c) of the belt table in table order.  The
+// neighbourhood reaches two nodes along each axis, so the wrapped (periodic)
+// or clamped coordinates of x-2..x+2, y-2..y+2, z-2..z+2 are formed once per
+// node and each neighbour's index is two additions; the pair offsets come
+// from the compile-time table, the coefficients (c_d, w, p) from device
+// constant data, so the sums are the same floating-point expressions as a
+// loop over the table.  Only the kernels of multirange simulations carry it
+// (the extended-force instantiation of the two-component model).
 static __constant__ BeltTable kBeltTab = make_belt_table();
+
+template <int B, class T, class FT>
+__device__ __forceinline__ void belt_pair(const FT *__restrict__ psR, const FT *__restrict__ psB, const int (&ox)[5],
+                                          const int (&oy)[5], const int (&oz)[5], T (&aR)[3], T (&aB)[3],
+                                          T (&rR)[3], T (&rB)[3])
+{
+    constexpr int cx = Belts::tab.c[B][0], cy = Belts::tab.c[B][1], cz = Belts::tab.c[B][2];
+    static_assert(cx >= -2 && cx <= 2 && cy >= -2 && cy <= 2 && cz >= -2 && cz <= 2, "two-node reach");
+    const unsigned mp = (unsigned)(ox[2 + cx] + oy[2 + cy] + oz[2 + cz]);
+    const unsigned mm = (unsigned)(ox[2 - cx] + oy[2 - cy] + oz[2 - cz]);
+    const T dR = (T)psR[mp] - (T)psR[mm];
+    const T dB = (T)psB[mp] - (T)psB[mm];
+    const T wb = (T)kBeltTab.w[B], pb = (T)kBeltTab.p[B];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T cd = (T)kBeltTab.c[B][d];
+        aR[d] += wb * dR * cd;
+        aB[d] += wb * dB * cd;
+        rR[d] += pb * dR * cd;
+        rB[d] += pb * dB * cd;
+    }
+}
+
+template <class T, class FT, int... B>
+__device__ __forceinline__ void belt_sums(std::integer_sequence<int, B...>, const FT *__restrict__ psR,
+                                          const FT *__restrict__ psB, const int (&ox)[5], const int (&oy)[5],
+                                          const int (&oz)[5], T (&aR)[3], T (&aB)[3], T (&rR)[3], T (&rB)[3])
+{
+    (belt_pair<B, T>(psR, psB, ox, oy, oz, aR, aB, rR, rB), ...);
+}
 
 template <class T, class FT>
 __device__ __forceinline__ void add_multirange(const KParams &P, const FT *__restrict__ field, int x, int y, int z,
                                                long long n, T (&FR)[3], T (&FB)[3])
 {
     const FT *psR = field + 2 * P.N, *psB = field + 3 * P.N;
+    const int nx = P.nx, sxy = P.nx * P.ny;   // N < 2^31: 32-bit offsets
+    int ox[5], oy[5], oz[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        ox[k] = stencil_coord(x + k - 2, P.nx, P.bc[0]);
+        oy[k] = nx * stencil_coord(y + k - 2, P.ny, P.bc[1]);
+        oz[k] = sxy * stencil_coord(z + k - 2, P.nz, P.bc[2]);
+    }
     T aR[3] = {T(0), T(0), T(0)}, aB[3] = {T(0), T(0), T(0)};
     T rR[3] = {T(0), T(0), T(0)}, rB[3] = {T(0), T(0), T(0)};
-#pragma unroll 1
-    for (int b = 0; b < Belts::n; ++b) {
-        const int cc[3] = {kBeltTab.c[b][0], kBeltTab.c[b][1], kBeltTab.c[b][2]};
-        const long long mp = stencil_at(P, x, y, z, cc[0], cc[1], cc[2]);
-        const long long mm = stencil_at(P, x, y, z, -cc[0], -cc[1], -cc[2]);
-        const T dR = (T)psR[mp] - (T)psR[mm];
-        const T dB = (T)psB[mp] - (T)psB[mm];
-        const T wb = (T)kBeltTab.w[b], pb = (T)kBeltTab.p[b];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T cd = (T)cc[d];
-            aR[d] += wb * dR * cd;
-            aB[d] += wb * dB * cd;
-            rR[d] += pb * dR * cd;
-            rB[d] += pb * dB * cd;
-        }
-    }
+    belt_sums<T>(std::make_integer_sequence<int, Belts::n>(), psR, psB, ox, oy, oz, aR, aB, rR, rB);
     const T pR = (T)psR[n], pB = (T)psB[n];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -321,6 +349,7 @@ __device__ __forceinline__ void repulsion_force(const KParams &P, const FT *__re
 
 // ---------------------------------------------------------------------------
 // Collide + push-stream of one node, reading stencil inputs from the field.
+// REP: with the model's extended force (CG repulsion, SC_MC multirange).
 // ---------------------------------------------------------------------------
 template <class L, int PR, int MODEL, bool REP>
 __device__ __forceinline__ void collide_body(const KParams &P, const typename Prec<PR>::S *__restrict__ src,
@@ -395,7 +424,7 @@ __device__ __forceinline__ void collide_body(const KParams &P, const typename Pr
             FR[d] = -H.xpref * (C)rR * sB[d];
             FB[d] = -H.xpref * (C)rB * sR[d];
         }
-        if (P.multirange) add_multirange<C>(P, field, x, y, z, n, FR, FB);
+        if constexpr (REP) add_multirange<C>(P, field, x, y, z, n, FR, FB);   // extended force: multirange
 #pragma unroll
         for (int d = 0; d < 3; ++d) u[d] = (C)((j[d] + M(0.5) * ((M)FR[d] + (M)FB[d])) * ir);
         sc_collide_component<L, C, M>(g[0], H.om[0], dr[0], rR, u, FR, H.rho0[0], H.corrM[0], H.shiftM[0]);

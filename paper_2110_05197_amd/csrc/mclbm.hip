@@ -48,6 +48,14 @@ bool multirange_of(const mclbm_params &p)
 {
     return p.Ga_R != 0.0 || p.Ga_B != 0.0 || p.Gr_R != 0.0 || p.Gr_B != 0.0;
 }
+
+// The kernels with the model's extended force (Ops REP): the colour-gradient
+// repulsion, or the two-component Shan-Chen multirange forces.
+bool extended_of(const mclbm_params &p)
+{
+    return (p.model == MCLBM_CG && p.Pi != 0.0) || multirange_of(p);
+}
+
 // stencil-field values per node: CG drho_R, drho_B, rho^N; SC_MP psi; SC_MC
 // drho_R, drho_B (+ psi_R, psi_B with the multirange forces)
 int nfield_of(const mclbm_params &p)
@@ -191,7 +199,7 @@ mclbm_status validate(const mclbm_params *p)
             return fail(MCLBM_EINVAL, "multirange couplings must be finite");
     }
     if (p->kernel < 0 || p->kernel > 2) return fail(MCLBM_EINVAL, "bad kernel choice %d", p->kernel);
-    const Ops *ops = get_ops(p->lattice, p->precision, p->model, p->model == MCLBM_CG && p->Pi != 0.0);
+    const Ops *ops = get_ops(p->lattice, p->precision, p->model, extended_of(*p));
     if (!ops) return fail(MCLBM_EUNSUPPORTED, "combination not provided");
     if (p->kernel == MCLBM_KERNEL_FUSED && !fused_ok(*p, ops))
         return fail(MCLBM_EUNSUPPORTED, "no fused kernel for this lattice/model/precision/size");
@@ -642,7 +650,7 @@ mclbm_status mclbm_create(const mclbm_params *p, void *d_state, size_t bytes, vo
     if (!sim) return fail(MCLBM_ENOMEM, "host allocation failed");
     sim->prm = *p;
     sim->kp = make_kparams(*p);
-    sim->ops = get_ops(p->lattice, p->precision, p->model, p->model == MCLBM_CG && p->Pi != 0.0);
+    sim->ops = get_ops(p->lattice, p->precision, p->model, extended_of(*p));
     sim->lay = lay;
     sim->base = (char *)d_state;
     sim->f[0] = sim->base;
@@ -932,7 +940,7 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
     std::vector<std::tuple<int, int, int, int>> keys;
     for (int i = 0; i < n; ++i) {
         const mclbm_params &p = sims[i]->prm;
-        auto key = std::make_tuple(p.lattice, p.precision, p.model, (int)(p.model == MCLBM_CG && p.Pi != 0.0));
+        auto key = std::make_tuple(p.lattice, p.precision, p.model, (int)extended_of(p));
         if (!groups.count(key)) keys.push_back(key);
         groups[key].push_back(i);
     }

@@ -51,7 +51,12 @@ inline long long outflow_count(const KParams &P)
     return c;
 }
 
-// Fused one-pass step (fused.hpp) for D3Q19 and D2Q9 without the repulsion
+// REP: the model's extended force, which reaches beyond the one-node halo of
+// the one-pass kernels: the repulsion force of the colour-gradient model
+// (normals at the neighbours), the multirange forces of the two-component
+// Shan-Chen model (two nodes out).  Its simulations step on the two-pass
+// kernels.
+// Fused one-pass step (fused.hpp) for D3Q19 and D2Q9 without an extended
 // force.
 template <class L, int PR, int MODEL, bool REP> constexpr bool fused_available()
 {
@@ -97,7 +102,7 @@ struct OpsT final : Ops {
         if (!done) {
             hipLaunchKernelGGL((k_density<L, PR, MODEL>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
                                (const S *)src, (FT *)field, flag);
-            if constexpr (REP)
+            if constexpr (REP && MODEL == CG)
                 hipLaunchKernelGGL((k_gradN<L, PR>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
                                    (const FT *)field, (FT *)gfield);
             hipLaunchKernelGGL((k_collide<L, PR, MODEL, REP>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
@@ -160,7 +165,7 @@ struct OpsT final : Ops {
     {
         if (blocks > 0) {
             hipLaunchKernelGGL((kb_density<L, PR, MODEL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
-            if constexpr (REP)
+            if constexpr (REP && MODEL == CG)
                 hipLaunchKernelGGL((kb_gradN<L, PR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
             hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
         }
@@ -189,7 +194,13 @@ const Ops *ops_for_model(int model, bool rep)
     static const OpsT<L, PR, SC_MC, false> mc;
     if (model == CG) return rep ? (const Ops *)&cgr : (const Ops *)&cg;
     if (model == SC_MP) return &mp;
-    if (model == SC_MC) return &mc;
+    if (model == SC_MC) {
+        if constexpr (L::Q == 19) {   // the multirange neighbourhood is three-dimensional
+            static const OpsT<L, PR, SC_MC, true> mcm;
+            if (rep) return &mcm;
+        }
+        return rep ? nullptr : &mc;
+    }
     return nullptr;
 }
 template <int PR>
