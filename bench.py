@@ -98,7 +98,8 @@ def workload_fields(n: int, seed: int = 0, model: str = "CG", lattice: str = "D3
     return rR, rB
 
 
-def params(n: int, precision: int = 1, kernel: int = 0, model: str = "CG", lattice: str = "D3Q19"):
+def params(n: int, precision: int = 1, kernel: int = 0, model: str = "CG", lattice: str = "D3Q19",
+           conserve: bool = False):
     import paper_2110_05197_amd as M
     nz, ny, nx = shape_of(n, lattice)
     base = dict(lattice=M.D2Q9 if lattice == "D2Q9" else M.D3Q19, precision=precision, nx=nx, ny=ny,
@@ -109,7 +110,7 @@ def params(n: int, precision: int = 1, kernel: int = 0, model: str = "CG", latti
         return M.make_params(model=M.SC_MC, G_RB=SC_MC_GRB, tau_R=1.0, tau_B=1.0, rho0_R=1.0,
                              rho0_B=1.0, **base)
     return M.make_params(model=M.CG, rho0_R=1.0, rho0_B=1.0, tau_R=1.0, tau_B=1.0, A=0.005,
-                         beta=0.7, **base)
+                         beta=0.7, conserve_mass=int(conserve), **base)
 
 
 def stream_probe(n: int):
@@ -327,6 +328,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the sweep-serving leg")
     ap.add_argument("--serve-full", action="store_true",
                     help="serve the full 256-request trace (minutes) instead of the reduced one")
+    ap.add_argument("--conserve-mass", action="store_true",
+                    help="CG, FP32 or mixed storage: keep each colour's node mass to one rounding per step")
     ap.add_argument("--next-rows", action="store_true",
                     help="time the multirange Shan-Chen step and the interface observables on the workload")
     ap.add_argument("--copy-probe", action="store_true",
@@ -412,7 +415,7 @@ def main():
           f"{'x'.join(str(d) for d in shape_of(n, args.lattice)[::-1] if d > 1)} nodes)",
           file=sys.stderr, flush=True)
     rR, rB = workload_fields(n, 0, args.model, args.lattice)
-    p = params(n, args.precision, args.kernel, args.model, args.lattice)
+    p = params(n, args.precision, args.kernel, args.model, args.lattice, args.conserve_mass)
     sim = M.Sim(p)
     sim.init_equilibrium(rR, rB)
     stream = torch.cuda.current_stream()

@@ -30,7 +30,7 @@ FP64, FP32, MIXED, FP16 = 0, 1, 2, 3
 PERIODIC, WALL, OUTFLOW = 0, 1, 2
 KERNEL_AUTO, KERNEL_TWO_PASS, KERNEL_FUSED = 0, 1, 2
 RUNNING, DONE, STOPPED_DIVERGED = 0, 1, 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class MclbmError(RuntimeError):
@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("Pi", ctypes.c_double), ("chi", ctypes.c_double),
         ("Ga_R", ctypes.c_double), ("Ga_B", ctypes.c_double),
         ("Gr_R", ctypes.c_double), ("Gr_B", ctypes.c_double),
+        ("conserve_mass", ctypes.c_int32),
     ]
 
 

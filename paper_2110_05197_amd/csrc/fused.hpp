@@ -79,8 +79,11 @@ constexpr int fused_lds_bytes()
 // arithmetic, LA the one that places neighbours: both D3Q19, or D2Q9 and
 // D2Q9Z for a 2-D box seen as nx x 1 x ny (TY = 1, halo columns only), so
 // that a 2-D node's arithmetic is the two-pass kernels', operation for
-// operation.
-template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool EDGE = false, class L = D3Q19, class LA = L>
+// operation.  CONS: whether the collision keeps each colour's node mass
+// (kConsNever / kConsAsked / kConsAlways, see cg_collide): the batched
+// kernels ask each simulation, the solo launches choose a kernel.
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool EDGE = false, class L = D3Q19, class LA = L,
+          int CONS = kConsShared<PR>>
 __device__ __forceinline__ void fused_column(const KParams &P, const typename Prec<PR>::S *__restrict__ src,
                                              typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int x0, int y0,
                                              int z0, int z1, unsigned char *smem)
@@ -201,7 +204,7 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
 #pragma unroll
                 for (int dd = 0; dd < 3; ++dd) { gR[dd] *= C(3); gB[dd] *= C(3); gN[dd] *= C(3); }
                 const C F0[3] = {C(0), C(0), C(0)};
-                cg_collide<L, C, M, false>(H, c, drc, jc, gR, gB, gN, F0);
+                cg_collide<L, C, M, false, CONS>(H, c, drc, jc, gR, gB, gN, F0);
             } else if constexpr (MODEL == SC_MP) {
                 C s3[3];
                 stencil_sum<L>(v[0], s3);
@@ -273,7 +276,8 @@ __device__ __forceinline__ void fused_column(const KParams &P, const typename Pr
 }
 
 // RAGGED: TX does not divide nx, and the last column in x is an edge column.
-template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool RAGGED, class L = D3Q19, class LA = L>
+template <int PR, int MODEL, int TX, int TY, bool PERIODIC, bool RAGGED, class L = D3Q19, class LA = L,
+          bool CONS = false>
 __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec<PR>::S *__restrict__ src,
                                                   typename Prec<PR>::S *__restrict__ dst, unsigned *flag, int TZ,
                                                   int tiles_x, int tiles_y)
@@ -282,13 +286,14 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ, z1 = min(z0 + TZ, P.nz);
+    constexpr int cons = CONS ? kConsAlways : kConsNever;
     if constexpr (RAGGED) {
         if (bx == tiles_x - 1) {
-            fused_column<PR, MODEL, TX, TY, PERIODIC, true, L, LA>(P, src, dst, flag, x0, y0, z0, z1, smem);
+            fused_column<PR, MODEL, TX, TY, PERIODIC, true, L, LA, cons>(P, src, dst, flag, x0, y0, z0, z1, smem);
             return;
         }
     }
-    fused_column<PR, MODEL, TX, TY, PERIODIC, false, L, LA>(P, src, dst, flag, x0, y0, z0, z1, smem);
+    fused_column<PR, MODEL, TX, TY, PERIODIC, false, L, LA, cons>(P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
 // Batched one-pass step: the blocks of all eligible simulations of a group
@@ -452,8 +457,8 @@ inline bool fused_shape(const KParams &P, FusedShape &sh, bool wide = false)
     return true;
 }
 
-template <int PR, int MODEL, int TX, int TY, bool RAGGED>
-void launch_fused_shape(const KParams &P, const void *src, void *dst, unsigned *flag, int tz, hipStream_t s)
+template <int PR, int MODEL, int TX, int TY, bool RAGGED, bool CONS>
+void launch_fused_kernel(const KParams &P, const void *src, void *dst, unsigned *flag, int tz, hipStream_t s)
 {
     const int tiles_x = (P.nx + TX - 1) / TX, tiles_y = P.ny / TY, tiles_z = (P.nz + tz - 1) / tz;
     const dim3 grid(tiles_x * tiles_y * tiles_z), block(TX * TY);
@@ -461,18 +466,32 @@ void launch_fused_shape(const KParams &P, const void *src, void *dst, unsigned *
     constexpr int lds = fused_lds_bytes<PR, MODEL, TX, TY>();
     static bool attr_set = false;   // raise the dynamic-LDS limit once per process
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, true, RAGGED>,
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, true, RAGGED, D3Q19, D3Q19, CONS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, false, RAGGED>,
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, TX, TY, false, RAGGED, D3Q19, D3Q19, CONS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
     if (P.bc[0] == 0 && P.bc[1] == 0 && P.bc[2] == 0)
-        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, true, RAGGED>), grid, block, lds, s, P, (const S *)src,
-                           (S *)dst, flag, tz, tiles_x, tiles_y);
+        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, true, RAGGED, D3Q19, D3Q19, CONS>), grid, block, lds, s, P,
+                           (const S *)src, (S *)dst, flag, tz, tiles_x, tiles_y);
     else
-        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, false, RAGGED>), grid, block, lds, s, P, (const S *)src,
-                           (S *)dst, flag, tz, tiles_x, tiles_y);
+        hipLaunchKernelGGL((k_fused<PR, MODEL, TX, TY, false, RAGGED, D3Q19, D3Q19, CONS>), grid, block, lds, s, P,
+                           (const S *)src, (S *)dst, flag, tz, tiles_x, tiles_y);
+}
+
+// The mass-keeping collision has kernels of its own, so that the default
+// step carries none of it.
+template <int PR, int MODEL, int TX, int TY, bool RAGGED>
+void launch_fused_shape(const KParams &P, const void *src, void *dst, unsigned *flag, int tz, hipStream_t s)
+{
+    if constexpr (kConserveRest<PR> && MODEL == CG) {
+        if (P.conserve) {
+            launch_fused_kernel<PR, MODEL, TX, TY, RAGGED, true>(P, src, dst, flag, tz, s);
+            return;
+        }
+    }
+    launch_fused_kernel<PR, MODEL, TX, TY, RAGGED, false>(P, src, dst, flag, tz, s);
 }
 
 template <int PR, int MODEL>
@@ -514,7 +533,7 @@ inline void fused2d_rows(const KParams &Q, int &tiles_x, int &tz)
     tz = (Q.nz + tiles_z - 1) / tiles_z;
 }
 
-template <int PR, int MODEL, bool RAGGED>
+template <int PR, int MODEL, bool RAGGED, bool CONS>
 void launch_fused2d_shape(const KParams &Q, const void *src, void *dst, unsigned *flag, hipStream_t s)
 {
     int tiles_x = 0, tz = 0;
@@ -524,17 +543,17 @@ void launch_fused2d_shape(const KParams &Q, const void *src, void *dst, unsigned
     constexpr int lds = fused_lds_bytes<PR, MODEL, k2dTX, 1, D2Q9Z>();
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, k2dTX, 1, true, RAGGED, D2Q9, D2Q9Z>,
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, k2dTX, 1, true, RAGGED, D2Q9, D2Q9Z, CONS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, k2dTX, 1, false, RAGGED, D2Q9, D2Q9Z>,
+        (void)hipFuncSetAttribute((const void *)k_fused<PR, MODEL, k2dTX, 1, false, RAGGED, D2Q9, D2Q9Z, CONS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         attr_set = true;
     }
     if (Q.bc[0] == 0 && Q.bc[2] == 0)
-        hipLaunchKernelGGL((k_fused<PR, MODEL, k2dTX, 1, true, RAGGED, D2Q9, D2Q9Z>), grid, block, lds, s, Q,
+        hipLaunchKernelGGL((k_fused<PR, MODEL, k2dTX, 1, true, RAGGED, D2Q9, D2Q9Z, CONS>), grid, block, lds, s, Q,
                            (const S *)src, (S *)dst, flag, tz, tiles_x, 1);
     else
-        hipLaunchKernelGGL((k_fused<PR, MODEL, k2dTX, 1, false, RAGGED, D2Q9, D2Q9Z>), grid, block, lds, s, Q,
+        hipLaunchKernelGGL((k_fused<PR, MODEL, k2dTX, 1, false, RAGGED, D2Q9, D2Q9Z, CONS>), grid, block, lds, s, Q,
                            (const S *)src, (S *)dst, flag, tz, tiles_x, 1);
 }
 
@@ -542,8 +561,15 @@ template <int PR, int MODEL>
 void launch_fused2d(const KParams &P, const void *src, void *dst, unsigned *flag, hipStream_t s)
 {
     const KParams Q = as_marching_2d(P);
-    if (Q.nx % k2dTX) launch_fused2d_shape<PR, MODEL, true>(Q, src, dst, flag, s);
-    else launch_fused2d_shape<PR, MODEL, false>(Q, src, dst, flag, s);
+    if constexpr (kConserveRest<PR> && MODEL == CG) {
+        if (P.conserve) {
+            if (Q.nx % k2dTX) launch_fused2d_shape<PR, MODEL, true, true>(Q, src, dst, flag, s);
+            else launch_fused2d_shape<PR, MODEL, false, true>(Q, src, dst, flag, s);
+            return;
+        }
+    }
+    if (Q.nx % k2dTX) launch_fused2d_shape<PR, MODEL, true, false>(Q, src, dst, flag, s);
+    else launch_fused2d_shape<PR, MODEL, false, false>(Q, src, dst, flag, s);
 }
 
 }  // namespace mclbm

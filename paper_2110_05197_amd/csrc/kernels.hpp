@@ -387,7 +387,7 @@ __device__ __forceinline__ void collide_body(const KParams &P, const typename Pr
         for (int d = 0; d < 3; ++d) { gR[d] *= C(3); gB[d] *= C(3); gN[d] *= C(3); }
         C F[3] = {C(0), C(0), C(0)};
         if constexpr (REP) repulsion_force<L>(P, field, gfield, x, y, z, n, F);
-        cg_collide<L, C, M, REP>(H, g, dr, j, gR, gB, gN, F);
+        cg_collide<L, C, M, REP, kConsShared<PR>>(H, g, dr, j, gR, gB, gN, F);
     } else if constexpr (MODEL == SC_MP) {
         C v[L::Q];
         v[0] = C(0);

@@ -171,6 +171,7 @@ mclbm_status validate(const mclbm_params *p)
     if (N >= (1LL << 31)) return fail(MCLBM_EUNSUPPORTED, "lattices of 2^31 nodes or more are not supported");
     for (int d = 0; d < 3; ++d)
         if (p->bc[d] < 0 || p->bc[d] > 2) return fail(MCLBM_EINVAL, "bad boundary type on axis %d", d);
+    if (p->conserve_mass != 0 && p->conserve_mass != 1) return fail(MCLBM_EINVAL, "conserve_mass must be 0 or 1");
     if (p->lattice == MCLBM_D2Q9 && p->bc[2] != MCLBM_PERIODIC) return fail(MCLBM_EINVAL, "D2Q9: bc[2] must be periodic");
     if (!(p->tau_R > 0.5)) return fail(MCLBM_EINVAL, "tau_R must be > 1/2");
     if (p->model != MCLBM_SC_MP && !(p->tau_B > 0.5)) return fail(MCLBM_EINVAL, "tau_B must be > 1/2");
@@ -230,6 +231,8 @@ KParams make_kparams(const mclbm_params &p)
     K.N = (long long)p.nx * p.ny * p.nz;
     K.S = pop_stride(p);
     K.enhanced = p.enhanced_eq ? 1 : 0;
+    K.conserve = p.model == MCLBM_CG && (p.precision == MCLBM_FP32 || p.precision == MCLBM_MIXED)
+                 && p.conserve_mass ? 1 : 0;
     K.has_outflow = (p.bc[0] == MCLBM_OUTFLOW || p.bc[1] == MCLBM_OUTFLOW || p.bc[2] == MCLBM_OUTFLOW) ? 1 : 0;
     K.rho0[0] = p.rho0_R;
     K.rho0[1] = p.model == MCLBM_SC_MP ? 0.0 : p.rho0_B;

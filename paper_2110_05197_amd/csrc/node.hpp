@@ -25,6 +25,11 @@ template <> struct Prec<0> { using S = double;   using C = double; using M = dou
 template <> struct Prec<1> { using S = float;    using C = float;  using M = float;  using F = float; };
 template <> struct Prec<2> { using S = float;    using C = float;  using M = double; using F = float; };
 template <> struct Prec<3> { using S = _Float16; using C = float;  using M = float;  using F = float; };
+// precisions whose colour-gradient collision can keep each colour's node mass
+// to one rounding (mclbm_params.conserve_mass), and the mode of the kernels
+// shared by simulations that do and do not ask for it
+template <int PR> constexpr bool kConserveRest = PR == 1 || PR == 2;
+template <int PR> constexpr int kConsShared = kConserveRest<PR> ? 1 : 0;
 
 // Parameters of one simulation as the kernels see them (host-derived).
 struct KParams {
@@ -34,6 +39,7 @@ struct KParams {
     long long S;         // storage words from one population array to the next (>= N)
     int enhanced;
     int has_outflow;
+    int conserve;        // CG, FP32 / mixed storage: keep each colour's node mass to one rounding
     double rho0[2];      // reference densities of the deviation storage
     double phi[2][3];    // CG: phi_i^k per group; SC: w per group
     double shift[2][3];  // storage reference per group; sum_i shift = rho0[k] exactly
@@ -67,6 +73,7 @@ struct HP {
     C G, psi_rho0, xpref, Pi, chi;
     C Ga[2], Gr[2];
     int enhanced;
+    int conserve;
 };
 
 template <class C, class M>
@@ -99,6 +106,7 @@ __device__ __forceinline__ HP<C, M> make_hp(const KParams &P)
     H.Pi = (C)P.Pi;
     H.chi = (C)P.chi;
     H.enhanced = P.enhanced;
+    H.conserve = P.conserve;
     return H;
 }
 
@@ -248,11 +256,32 @@ __device__ __forceinline__ T rest_dev(bool present, T dr, T rho, T phi, T corr, 
 //   X = (rho_R/rho) f*_B - (rho_B/rho) f*_R,   f_B,out = f*_B - X - t,
 // which is exactly zero where one colour is absent.
 // ---------------------------------------------------------------------------
-template <class L, class C, class M, bool FORCED>
+// CONS (FP32 and mixed storage, whose arithmetic type is the storage type):
+// each colour's node mass is kept exactly, up to one rounding: the rest
+// population is set last to the input populations' sum minus the other
+// outputs, both sums in FP64.  Without it the FP32 roundings of the pairs
+// +-t_i of the recolouring (and of the other sums) leave a bias of about 1e-7
+// of the colour mass per step at interfaces.  kConsNever: not compiled in;
+// kConsAsked: when the simulation asks for it (H.conserve; kernels shared by
+// simulations either way); kConsAlways: unconditionally (kernels launched
+// only for simulations that ask for it).  Off, the arithmetic is the same as
+// without this code.
+constexpr int kConsNever = 0, kConsAsked = 1, kConsAlways = 2;
+template <class L, class C, class M, bool FORCED, int CONS = kConsNever>
 __device__ __forceinline__ void cg_collide(const HP<C, M> &H, C (&g)[2][L::Q], const M (&dr)[2],
                                            const M (&j)[3], const C (&gR)[3], const C (&gB)[3],
                                            const C (&gN)[3], const C (&F)[3])
 {
+    const bool cons = CONS == kConsAlways || (CONS == kConsAsked && H.conserve);
+    double din[2] = {0.0, 0.0};
+    if constexpr (CONS != kConsNever) {
+        if (cons) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) din[k] += (double)g[k][i];
+        }
+    }
     const M rR = H.rho0[0] + dr[0];
     const M rB = H.rho0[1] + dr[1];
     const M r = rR + rB;
@@ -350,6 +379,17 @@ __device__ __forceinline__ void cg_collide(const HP<C, M> &H, C (&g)[2][L::Q], c
         g[1][i] = (C)(sBp - Xp - t);
         g[0][i + 1] = (C)((M)sRm + Xm - t);
         g[1][i + 1] = (C)(sBm - Xm + t);
+    }
+    if constexpr (CONS != kConsNever) {
+        if (cons) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                double out = 0.0;
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) out += (double)g[k][i];
+                g[k][0] = (C)(din[k] - out);
+            }
+        }
     }
 }
 

@@ -43,7 +43,7 @@ def test_version_and_status_strings(M):
 
 def test_defaults(M):
     p = M.params_default(M.D3Q19, M.CG)
-    assert p["abi_version"] == 2 and p["beta"] == 0.7 and p["alpha_B"] == 0.2
+    assert p["abi_version"] == 3 and p["beta"] == 0.7 and p["alpha_B"] == 0.2 and p["conserve_mass"] == 0
     assert (p["nx"], p["ny"], p["nz"]) == (64, 64, 64)
     assert M.params_default(M.D2Q9, M.CG)["nz"] == 1
 
@@ -109,7 +109,7 @@ def test_population_stride_padding(M, lattice, model, prec, shape, word, arrays)
 
 @pytest.mark.parametrize("bad", [
     dict(tau_R=0.5), dict(tau_B=0.4), dict(beta=1.5), dict(rho0_B=2.0), dict(alpha_B=1.0),
-    dict(nx=1), dict(nz=1), dict(bc=(0, 3, 0)), dict(precision=7), dict(abi_version=9),
+    dict(nx=1), dict(nz=1), dict(bc=(0, 3, 0)), dict(precision=7), dict(abi_version=9), dict(conserve_mass=2),
     dict(kernel=5), dict(A=-1.0),
 ])
 def test_validation_rejects(M, bad):

@@ -330,6 +330,56 @@ def test_fp32_mass_conservation(M):
     assert abs(o1["mass_B"] - o0["mass_B"]) / o0["mass_B"] < 500 * 2e-7
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+def test_conserve_mass_option(M, orc, prec):
+    """conserve_mass = 1 (FP32 and mixed storage): the rest population is set
+    from FP64 sums so that each colour's node mass is kept to one rounding.
+    The populations stay within the precision's bound of the FP64 oracle after
+    100 steps, one-pass, two-pass and batched kernels still agree bit for bit,
+    and the colour masses drift far less over 500 steps.  What remains is the
+    single rounding of each node's rest population, whose errors do not quite
+    cancel (about 3 % of an ulp per interface node and step).  Measured on this
+    state: FP32 5.5e-7 against 7.5e-5 without (bound: 2e-9 per step and 20x
+    less); mixed precision, whose sums and recolouring are FP64 already,
+    2.1e-6 against 4.1e-6 (bound: 1e-8 per step and no more than without)."""
+    shape = (24, 16, 64)
+    p = M.make_params(lattice=M.D3Q19, precision=prec, nx=64, ny=16, nz=24, A=0.02, conserve_mass=1)
+    rR, rB, u = cg_droplet_case(shape, 21)
+    compare(M, orc, p, rR, rB, u, 100, 2e-5, kernel=2, label=f"conserve-mass prec={prec}")
+    _, f_fused = gpu_run(M, p, rR, rB, u, 40, kernel=2)
+    _, f_two = gpu_run(M, p, rR, rB, u, 40, kernel=1)
+    assert np.array_equal(f_fused, f_two)
+    sims = []
+    for q in (p, dict(p, conserve_mass=0)):
+        s = M.Sim(q)
+        s.init_equilibrium(rR, rB, u)
+        sims.append(s)
+    b = M.Batch(sims, [40, 40])
+    for _ in range(4):
+        b.step(10)
+    b.close()
+    assert np.array_equal(sims[0].export_f().cpu().numpy(), f_fused)
+    _, f_plain = gpu_run(M, dict(p, conserve_mass=0), rR, rB, u, 40, kernel=2)
+    assert np.array_equal(sims[1].export_f().cpu().numpy(), f_plain)
+    assert not np.array_equal(f_plain, f_fused)
+    for s in sims:
+        s.close()
+    drift = {}
+    for c in (1, 0):
+        sim = M.Sim(dict(p, conserve_mass=c))
+        sim.init_equilibrium(rR, rB, u)
+        o0 = sim.observables()
+        sim.step(500)
+        o1 = sim.observables()
+        drift[c] = max(abs(o1[k] - o0[k]) / o0[k] for k in ("mass_R", "mass_B"))
+        sim.close()
+    say(f"[conserve_mass] prec={prec}: 500-step colour-mass change {drift[1]:.2e} (off: {drift[0]:.2e})")
+    if prec == M.FP32:
+        assert drift[1] < 500 * 2e-9 and drift[1] < drift[0] / 20
+    else:
+        assert drift[1] < 500 * 1e-8 and drift[1] <= drift[0]
+
+
 @pytest.mark.parametrize("prec", [1, 0, 2, 3])
 def test_fused_equals_two_pass_bitwise(M, prec):
     """The one-pass kernel and the two-pass kernels give bitwise identical
