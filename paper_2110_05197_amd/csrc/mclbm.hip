@@ -456,10 +456,23 @@ __global__ __launch_bounds__(256) void k_ccl_jump(long long N, int *__restrict__
     }
 }
 
+// Component sizes: the lanes of a wave that carry one label add once, with
+// their count (consecutive nodes mostly share a label, and the few roots are
+// what every atomic would otherwise hit); each round retires at least the
+// leading lane's label, so the loop ends within 64 rounds.
 __global__ __launch_bounds__(256) void k_ccl_sizes(long long N, const int *__restrict__ lab, int *__restrict__ sizes)
 {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n < N && lab[n] >= 0) atomicAdd(&sizes[lab[n]], 1);
+    const int l = n < N ? lab[n] : -1;
+    bool pending = l >= 0;
+    for (unsigned long long m = __ballot(pending); m != 0ull; m = __ballot(pending)) {
+        const int lead = __ffsll((long long)m) - 1;
+        const int L = __shfl(l, lead);
+        const bool mine = pending && l == L;
+        const unsigned long long same = __ballot(mine);
+        if (mine && (int)(threadIdx.x & 63) == lead) atomicAdd(&sizes[L], (int)__popcll(same));
+        if (mine) pending = false;
+    }
 }
 
 // (root, size) pairs of the components, in any order (sorted on the host).
