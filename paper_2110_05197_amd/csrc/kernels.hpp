@@ -232,12 +232,11 @@ __device__ __forceinline__ bool density_body(const KParams &P, const typename Pr
 // sums taken over the pairs (c, -c) of the belt table in table order.  The
 // neighbourhood reaches two nodes along each axis, so the wrapped (periodic)
 // or clamped coordinates of x-2..x+2, y-2..y+2, z-2..z+2 are formed once per
-// node and each neighbour's index is two additions; the pair offsets come
-// from the compile-time table, the coefficients (c_d, w, p) from device
-// constant data, so the sums are the same floating-point expressions as a
-// loop over the table.  Only the kernels of multirange simulations carry it
-// (the extended-force instantiation of the two-component model).
-static __constant__ BeltTable kBeltTab = make_belt_table();
+// node and each neighbour's index is two additions.  The table is known at
+// compile time, so a pair adds only to the components where c is non-zero,
+// and to the attraction sums only on belt 1 (w = 0 beyond it).  Only the
+// kernels of multirange simulations carry it (the extended-force
+// instantiation of the two-component model).
 
 template <int B, class T, class FT>
 __device__ __forceinline__ void belt_pair(const FT *__restrict__ psR, const FT *__restrict__ psB, const int (&ox)[5],
@@ -246,19 +245,24 @@ __device__ __forceinline__ void belt_pair(const FT *__restrict__ psR, const FT *
 {
     constexpr int cx = Belts::tab.c[B][0], cy = Belts::tab.c[B][1], cz = Belts::tab.c[B][2];
     static_assert(cx >= -2 && cx <= 2 && cy >= -2 && cy <= 2 && cz >= -2 && cz <= 2, "two-node reach");
+    constexpr bool belt1 = Belts::tab.w[B] != 0.0;
     const unsigned mp = (unsigned)(ox[2 + cx] + oy[2 + cy] + oz[2 + cz]);
     const unsigned mm = (unsigned)(ox[2 - cx] + oy[2 - cy] + oz[2 - cz]);
     const T dR = (T)psR[mp] - (T)psR[mm];
     const T dB = (T)psB[mp] - (T)psB[mm];
-    const T wb = (T)kBeltTab.w[B], pb = (T)kBeltTab.p[B];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T cd = (T)kBeltTab.c[B][d];
-        aR[d] += wb * dR * cd;
-        aB[d] += wb * dB * cd;
-        rR[d] += pb * dR * cd;
-        rB[d] += pb * dB * cd;
-    }
+    const T qR = T(Belts::tab.p[B]) * dR, qB = T(Belts::tab.p[B]) * dB;
+    const T wR = belt1 ? T(Belts::tab.w[B]) * dR : T(0), wB = belt1 ? T(Belts::tab.w[B]) * dB : T(0);
+    auto add = [&](int d, T c) {
+        rR[d] += qR * c;
+        rB[d] += qB * c;
+        if constexpr (belt1) {
+            aR[d] += wR * c;
+            aB[d] += wB * c;
+        }
+    };
+    if constexpr (cx != 0) add(0, T(cx));
+    if constexpr (cy != 0) add(1, T(cy));
+    if constexpr (cz != 0) add(2, T(cz));
 }
 
 template <class T, class FT, int... B>
