@@ -335,7 +335,8 @@ def test_conserve_mass_option(M, orc, prec):
     """conserve_mass = 1 (FP32 and mixed storage): the rest population is set
     from FP64 sums so that each colour's node mass is kept to one rounding.
     The populations stay within the precision's bound of the FP64 oracle after
-    100 steps, one-pass, two-pass and batched kernels still agree bit for bit,
+    100 steps, one-pass, two-pass and batched kernels still agree bit for bit
+    (periodic, walls + outflow, and the D2Q9 row kernel),
     and the colour masses drift far less over 500 steps.  What remains is the
     single rounding of each node's rest population, whose errors do not quite
     cancel (about 3 % of an ulp per interface node and step).  Measured on this
@@ -364,6 +365,14 @@ def test_conserve_mass_option(M, orc, prec):
     assert not np.array_equal(f_plain, f_fused)
     for s in sims:
         s.close()
+    # the other conserving one-pass kernels: walls + outflow, and the D2Q9 rows
+    for q, shape2, seed in ((dict(p, bc=(1, 1, 2)), shape, 22),
+                            (M.make_params(lattice=M.D2Q9, precision=prec, nx=80, ny=48, nz=1, A=0.02,
+                                           conserve_mass=1), (1, 48, 80), 23)):
+        r2, b2, u2 = cg_droplet_case(shape2, seed, lattice=q["lattice"])
+        _, g1 = gpu_run(M, q, r2, b2, u2, 30, kernel=2)
+        _, g2 = gpu_run(M, q, r2, b2, u2, 30, kernel=1)
+        assert np.array_equal(g1, g2), q["lattice"]
     drift = {}
     for c in (1, 0):
         sim = M.Sim(dict(p, conserve_mass=c))
