@@ -273,11 +273,29 @@ __device__ __forceinline__ void belt_sums(std::integer_sequence<int, B...>, cons
     (belt_pair<B, T>(psR, psB, ox, oy, oz, aR, aB, rR, rB), ...);
 }
 
+// The forces from the belt sums and psi at the node.
+template <class T, class FT>
+__device__ __forceinline__ void multirange_forces(const KParams &P, const FT *__restrict__ psR,
+                                                  const FT *__restrict__ psB, const int (&ox)[5], const int (&oy)[5],
+                                                  const int (&oz)[5], T (&FR)[3], T (&FB)[3])
+{
+    T aR[3] = {T(0), T(0), T(0)}, aB[3] = {T(0), T(0), T(0)};
+    T rR[3] = {T(0), T(0), T(0)}, rB[3] = {T(0), T(0), T(0)};
+    belt_sums<T>(std::make_integer_sequence<int, Belts::n>(), psR, psB, ox, oy, oz, aR, aB, rR, rB);
+    const unsigned c = (unsigned)(ox[2] + oy[2] + oz[2]);
+    const T pR = (T)psR[c], pB = (T)psB[c];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        FR[d] += -(T)P.Ga[0] * pR * aR[d] - (T)P.Gr[0] * pR * rR[d];
+        FB[d] += -(T)P.Ga[1] * pB * aB[d] - (T)P.Gr[1] * pB * rB[d];
+    }
+}
+
+// psi read from the field in global memory, any thread layout.
 template <class T, class FT>
 __device__ __forceinline__ void add_multirange(const KParams &P, const FT *__restrict__ field, int x, int y, int z,
-                                               long long n, T (&FR)[3], T (&FB)[3])
+                                               T (&FR)[3], T (&FB)[3])
 {
-    const FT *psR = field + 2 * P.N, *psB = field + 3 * P.N;
     const int nx = P.nx, sxy = P.nx * P.ny;   // N < 2^31: 32-bit offsets
     int ox[5], oy[5], oz[5];
 #pragma unroll
@@ -286,15 +304,32 @@ __device__ __forceinline__ void add_multirange(const KParams &P, const FT *__res
         oy[k] = nx * stencil_coord(y + k - 2, P.ny, P.bc[1]);
         oz[k] = sxy * stencil_coord(z + k - 2, P.nz, P.bc[2]);
     }
-    T aR[3] = {T(0), T(0), T(0)}, aB[3] = {T(0), T(0), T(0)};
-    T rR[3] = {T(0), T(0), T(0)}, rB[3] = {T(0), T(0), T(0)};
-    belt_sums<T>(std::make_integer_sequence<int, Belts::n>(), psR, psB, ox, oy, oz, aR, aB, rR, rB);
-    const T pR = (T)psR[n], pB = (T)psB[n];
+    multirange_forces<T>(P, field + 2 * P.N, field + 3 * P.N, ox, oy, oz, FR, FB);
+}
+
+// psi read from a block's staged box in LDS (k_collide_mr): the box holds the
+// block's kMrTX x kMrTY nodes of one plane and two nodes around them, at the
+// wrapped or clamped coordinates the field read would use, so the sums see
+// the same values in the same order as add_multirange.
+constexpr int kMrTX = 64, kMrTY = 4;
+constexpr int kMrBX = kMrTX + 4, kMrBY = kMrTY + 4, kMrBZ = 5, kMrBox = kMrBX * kMrBY * kMrBZ;
+template <class FT> struct MrStaged {
+    const FT *R, *B;   // psi_R, psi_B: [z][y][x] of kMrBZ x kMrBY x kMrBX, two nodes around the tile
+    int tx, ty;        // the node's place in the block's tile
+};
+struct MrGlobal {};    // no staged box: read the field
+
+template <class T, class FT>
+__device__ __forceinline__ void add_multirange(const KParams &P, const MrStaged<FT> &s, T (&FR)[3], T (&FB)[3])
+{
+    int ox[5], oy[5], oz[5];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        FR[d] += -(T)P.Ga[0] * pR * aR[d] - (T)P.Gr[0] * pR * rR[d];
-        FB[d] += -(T)P.Ga[1] * pB * aB[d] - (T)P.Gr[1] * pB * rB[d];
+    for (int k = 0; k < 5; ++k) {
+        ox[k] = s.tx + k;
+        oy[k] = (s.ty + k) * kMrBX;
+        oz[k] = k * (kMrBX * kMrBY);
     }
+    multirange_forces<T>(P, s.R, s.B, ox, oy, oz, FR, FB);
 }
 
 // Gradient field of rho^N (repulsion variant): 3 sum w rho^N(x + c) c.
@@ -355,11 +390,14 @@ __device__ __forceinline__ void repulsion_force(const KParams &P, const FT *__re
 // Collide + push-stream of one node, reading stencil inputs from the field.
 // REP: with the model's extended force (CG repulsion, SC_MC multirange).
 // ---------------------------------------------------------------------------
-template <class L, int PR, int MODEL, bool REP>
+// MR: where the multirange forces read psi (MrGlobal: the field; MrStaged: a
+// box in LDS).
+template <class L, int PR, int MODEL, bool REP, class MR = MrGlobal>
 __device__ __forceinline__ void collide_body(const KParams &P, const typename Prec<PR>::S *__restrict__ src,
                                              typename Prec<PR>::S *__restrict__ dst,
                                              const typename Prec<PR>::F *__restrict__ field,
-                                             const typename Prec<PR>::F *__restrict__ gfield, long long n)
+                                             const typename Prec<PR>::F *__restrict__ gfield, long long n,
+                                             const MR &mr = MR{})
 {
     using C = typename Prec<PR>::C;
     using M = typename Prec<PR>::M;
@@ -428,7 +466,10 @@ __device__ __forceinline__ void collide_body(const KParams &P, const typename Pr
             FR[d] = -H.xpref * (C)rR * sB[d];
             FB[d] = -H.xpref * (C)rB * sR[d];
         }
-        if constexpr (REP) add_multirange<C>(P, field, x, y, z, n, FR, FB);   // extended force: multirange
+        if constexpr (REP) {   // extended force: multirange
+            if constexpr (std::is_same_v<MR, MrGlobal>) add_multirange<C>(P, field, x, y, z, FR, FB);
+            else add_multirange<C>(P, mr, FR, FB);
+        }
 #pragma unroll
         for (int d = 0; d < 3; ++d) u[d] = (C)((j[d] + M(0.5) * ((M)FR[d] + (M)FB[d])) * ir);
         sc_collide_component<L, C, M>(g[0], H.om[0], dr[0], rR, u, FR, H.rho0[0], H.corrM[0], H.shiftM[0]);
@@ -577,7 +618,7 @@ __device__ __forceinline__ bool node_state64(const KParams &P, const typename Pr
             for (int d = 0; d < 3; ++d) F[d] = -P.xpref * (rR * sB[d] + rB * sR[d]);
             if (P.multirange) {
                 double FR[3] = {0.0, 0.0, 0.0}, FB[3] = {0.0, 0.0, 0.0};
-                add_multirange<double>(P, field, x, y, z, n, FR, FB);
+                add_multirange<double>(P, field, x, y, z, FR, FB);
                 for (int d = 0; d < 3; ++d) F[d] += FR[d] + FB[d];
             }
         }

@@ -46,6 +46,82 @@ __global__ __launch_bounds__(kBlock) void k_collide(KParams P, const typename Pr
     if (n < P.N) collide_body<L, PR, MODEL, REP>(P, src, dst, field, gfield, n);
 }
 
+// Stages two fields (a, b) of a box in LDS: columns x0 - RCH .. x0 - RCH +
+// BX - 1, rows y0 - RCH .. and planes z - RCH .., [z][y][x], at the wrapped or
+// clamped coordinates a stencil read would use.  Each wave stages whole rows:
+// lane l holds columns l and, for l < BX - 64, 64 + l; a row's y and z
+// (wave-uniform) are wrapped once.  Coordinates past nx - 1 + RCH (ny - 1 +
+// RCH) are read by no node of the tile; their slots are left at zero.
+template <int BX, int BY, int BZ, int RCH, int THREADS, class FT>
+__device__ __forceinline__ void stage_box(const KParams &P, const FT *__restrict__ a, const FT *__restrict__ b,
+                                          FT *boxA, FT *boxB, int x0, int y0, int z)
+{
+    static_assert(BX >= 64 && BX <= 128 && THREADS % 64 == 0, "rows of 64 to 128 columns, whole waves");
+    const int nx = P.nx, sxy = P.nx * P.ny;   // N < 2^31: 32-bit offsets
+    const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
+    const int gx0 = x0 - RCH + lane, gx1 = x0 - RCH + 64 + lane;
+    const bool in0 = gx0 <= P.nx - 1 + RCH, in1 = lane < BX - 64 && gx1 <= P.nx - 1 + RCH;
+    const int qx0 = in0 ? stencil_coord(gx0, P.nx, P.bc[0]) : 0;
+    const int qx1 = in1 ? stencil_coord(gx1, P.nx, P.bc[0]) : 0;
+    for (int row = wave; row < BY * BZ; row += THREADS / 64) {
+        const int gy = y0 - RCH + row % BY, gz = z - RCH + row / BY;
+        FT a0 = FT(0), b0 = FT(0), a1 = FT(0), b1 = FT(0);
+        if (gy <= P.ny - 1 + RCH) {
+            const int base = nx * stencil_coord(gy, P.ny, P.bc[1]) + sxy * stencil_coord(gz, P.nz, P.bc[2]);
+            if (in0) {
+                a0 = a[(unsigned)(base + qx0)];
+                b0 = b[(unsigned)(base + qx0)];
+            }
+            if (in1) {
+                a1 = a[(unsigned)(base + qx1)];
+                b1 = b[(unsigned)(base + qx1)];
+            }
+        }
+        boxA[row * BX + lane] = a0;
+        boxB[row * BX + lane] = b0;
+        if (lane < BX - 64) {
+            boxA[row * BX + 64 + lane] = a1;
+            boxB[row * BX + 64 + lane] = b1;
+        }
+    }
+}
+
+// Collide pass of the multirange two-component Shan-Chen step (D3Q19): a
+// block takes a kMrTX x kMrTY tile of one plane (blocks ordered x tile, y
+// tile, z), first stages in LDS psi_R and psi_B of the tile and two nodes
+// around it, then collides its nodes with the multirange sums reading that
+// box (the one-node stencil of the cross force reads the field).
+// Waves per SIMD the multirange collide is compiled for.  Left to itself the
+// compiler gives FP32 136 registers a lane (three waves); a fourth wave, at
+// the cost of a dozen spilled registers, took the 256^3 step from 2.19 to
+// 2.06 ms.  Mixed (173 registers, two waves) fits three without spilling;
+// FP16 storage takes three and FP64 two, both without spilling.
+template <int PR> constexpr int kMrWaves = PR == 1 ? 4 : PR == 0 ? 2 : 3;
+
+template <int PR>
+__global__ __launch_bounds__(kMrTX *kMrTY) __attribute__((amdgpu_waves_per_eu(kMrWaves<PR>))) void k_collide_mr(KParams P, const typename Prec<PR>::S *__restrict__ src,
+                                                            typename Prec<PR>::S *__restrict__ dst,
+                                                            const typename Prec<PR>::F *__restrict__ field)
+{
+    using FT = typename Prec<PR>::F;
+    __shared__ FT psiR[kMrBox], psiB[kMrBox];
+    const int tiles_x = (P.nx + kMrTX - 1) / kMrTX, tiles_y = (P.ny + kMrTY - 1) / kMrTY;
+    const int b = (int)blockIdx.x;
+    const int x0 = (b % tiles_x) * kMrTX, y0 = ((b / tiles_x) % tiles_y) * kMrTY, z = b / (tiles_x * tiles_y);
+    stage_box<kMrBX, kMrBY, kMrBZ, 2, kMrTX * kMrTY>(P, field + 2 * P.N, field + 3 * P.N, psiR, psiB, x0, y0, z);
+    __syncthreads();
+    const int tx = (int)threadIdx.x % kMrTX, ty = (int)threadIdx.x / kMrTX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= P.nx || y >= P.ny) return;
+    const long long n = (long long)x + (long long)P.nx * ((long long)y + (long long)P.ny * z);
+    collide_body<D3Q19, PR, SC_MC, true>(P, src, dst, field, nullptr, n, MrStaged<FT>{psiR, psiB, tx, ty});
+}
+
+inline long long mr_blocks(const KParams &P)
+{
+    return (long long)((P.nx + kMrTX - 1) / kMrTX) * ((P.ny + kMrTY - 1) / kMrTY) * P.nz;
+}
+
 template <class L, int PR, int MODEL>
 __global__ __launch_bounds__(kBlock) void k_outflow(KParams P, typename Prec<PR>::S *__restrict__ dst,
                                                     long long count)

@@ -105,8 +105,12 @@ struct OpsT final : Ops {
             if constexpr (REP && MODEL == CG)
                 hipLaunchKernelGGL((k_gradN<L, PR>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
                                    (const FT *)field, (FT *)gfield);
-            hipLaunchKernelGGL((k_collide<L, PR, MODEL, REP>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
-                               (const S *)src, (S *)dst, (const FT *)field, (const FT *)gfield);
+            if constexpr (REP && MODEL == SC_MC && L::Q == 19)
+                hipLaunchKernelGGL((k_collide_mr<PR>), dim3((unsigned)mr_blocks(P)), dim3(kMrTX * kMrTY), 0, s, P,
+                                   (const S *)src, (S *)dst, (const FT *)field);
+            else
+                hipLaunchKernelGGL((k_collide<L, PR, MODEL, REP>), dim3(grid_of(P.N)), dim3(kBlock), 0, s, P,
+                                   (const S *)src, (S *)dst, (const FT *)field, (const FT *)gfield);
         }
         if (P.has_outflow) {
             const long long c = outflow_count(P);

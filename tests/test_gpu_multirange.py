@@ -92,3 +92,29 @@ def test_multirange_batch_invariance(M):
     assert np.array_equal(b.export_f().cpu().numpy(), f_solo_p)
     for s in (solo, solo_p, a, b):
         s.close()
+
+
+@pytest.mark.parametrize("prec,bc", [(1, (0, 0, 0)), (0, (1, 1, 2)), (2, (0, 0, 0)), (3, (1, 1, 2))])
+def test_multirange_staged_box_equals_field_reads(M, prec, bc):
+    """The solo collide stages psi in LDS per 64 x 4 tile (and is compiled
+    for a wave count of its own per precision); the batched one reads the
+    field.  On a box of several tiles with ragged last tiles in x
+    (130 = 64 + 64 + 2) and y (22 = 5 * 4 + 2) the two agree bitwise in every
+    precision."""
+    shape = (20, 22, 130)
+    rA, rB, u = fields(shape, 11)
+    p = M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=prec, nx=130, ny=22, nz=20, bc=bc, **BENZI)
+    solo = M.Sim(p)
+    solo.init_equilibrium(rA, rB, u)
+    solo.step(20)
+    f_solo = solo.export_f().cpu().numpy()
+    a = M.Sim(p)
+    a.init_equilibrium(rA, rB, u)
+    batch = M.Batch([a], [20])
+    batch.step(20)
+    batch.close()
+    say(f"[multirange staged] prec={prec} bc={bc}: max |diff| "
+        f"{float(np.abs(a.export_f().cpu().numpy() - f_solo).max()):.3e}")
+    assert np.array_equal(a.export_f().cpu().numpy(), f_solo)
+    for s in (solo, a):
+        s.close()
