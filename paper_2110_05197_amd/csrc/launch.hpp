@@ -86,11 +86,6 @@ __device__ __forceinline__ void stage_box(const KParams &P, const FT *__restrict
     }
 }
 
-// Collide pass of the multirange two-component Shan-Chen step (D3Q19): a
-// block takes a kMrTX x kMrTY tile of one plane (blocks ordered x tile, y
-// tile, z), first stages in LDS psi_R and psi_B of the tile and two nodes
-// around it, then collides its nodes with the multirange sums reading that
-// box (the one-node stencil of the cross force reads the field).
 // Waves per SIMD the multirange collide is compiled for.  Left to itself the
 // compiler gives FP32 136 registers a lane (three waves); a fourth wave, at
 // the cost of a dozen spilled registers, took the 256^3 step from 2.19 to
@@ -98,10 +93,15 @@ __device__ __forceinline__ void stage_box(const KParams &P, const FT *__restrict
 // FP16 storage takes three and FP64 two, both without spilling.
 template <int PR> constexpr int kMrWaves = PR == 1 ? 4 : PR == 0 ? 2 : 3;
 
+// Collide pass of the multirange two-component Shan-Chen step (D3Q19): a
+// block takes a kMrTX x kMrTY tile of one plane (blocks ordered x tile, y
+// tile, z), first stages in LDS psi_R and psi_B of the tile and two nodes
+// around it, then collides its nodes with the multirange sums reading that
+// box (the one-node stencil of the cross force reads the field).
 template <int PR>
-__global__ __launch_bounds__(kMrTX *kMrTY) __attribute__((amdgpu_waves_per_eu(kMrWaves<PR>))) void k_collide_mr(KParams P, const typename Prec<PR>::S *__restrict__ src,
-                                                            typename Prec<PR>::S *__restrict__ dst,
-                                                            const typename Prec<PR>::F *__restrict__ field)
+__global__ __launch_bounds__(kMrTX *kMrTY) __attribute__((amdgpu_waves_per_eu(kMrWaves<PR>)))
+void k_collide_mr(KParams P, const typename Prec<PR>::S *__restrict__ src, typename Prec<PR>::S *__restrict__ dst,
+                  const typename Prec<PR>::F *__restrict__ field)
 {
     using FT = typename Prec<PR>::F;
     __shared__ FT psiR[kMrBox], psiB[kMrBox];
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void kb_density(SimDesc *D, int nsims)
 }
 
 template <class L, int PR, int MODEL, bool REP>
-__global__ __launch_bounds__(kBlock) void kb_collide(SimDesc *D, int nsims)
+__device__ __forceinline__ void kb_collide_body(SimDesc *D, int nsims)
 {
     const int s = find_sim(D, nsims, blockIdx.x, false);
     const SimDesc &d = D[s];
@@ -263,6 +263,26 @@ __global__ __launch_bounds__(kBlock) void kb_collide(SimDesc *D, int nsims)
                                         global_ptr<const typename Prec<PR>::F>(d.field),
                                         global_ptr<const typename Prec<PR>::F>(d.gfield), n);
 }
+
+template <class L, int PR, int MODEL, bool REP>
+__global__ __launch_bounds__(kBlock) void kb_collide(SimDesc *D, int nsims)
+{
+    kb_collide_body<L, PR, MODEL, REP>(D, nsims);
+}
+
+// The same kernel compiled for three waves per SIMD, for the D3Q19 mixed
+// colour-gradient collide: left to itself the compiler gives it 172
+// registers a lane (two waves); at three it holds 168 with no spill, and a
+// batch of eight 80^3 two-pass lattices stepped in 0.450 instead of 0.483 ms.
+// (Caps that make the other collides spill slowed them, up to twofold.)
+template <class L, int PR, int MODEL, bool REP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void kb_collide_w3(SimDesc *D, int nsims)
+{
+    kb_collide_body<L, PR, MODEL, REP>(D, nsims);
+}
+template <class L, int PR, int MODEL, bool REP>
+constexpr bool kb_collide_three_waves = L::Q == 19 && PR == 2 && MODEL == CG && !REP;
 
 template <class L, int PR>
 __global__ __launch_bounds__(kBlock) void kb_gradN(SimDesc *D, int nsims)

@@ -171,7 +171,10 @@ struct OpsT final : Ops {
             hipLaunchKernelGGL((kb_density<L, PR, MODEL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
             if constexpr (REP && MODEL == CG)
                 hipLaunchKernelGGL((kb_gradN<L, PR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
-            hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
+            if constexpr (kb_collide_three_waves<L, PR, MODEL, REP>)
+                hipLaunchKernelGGL((kb_collide_w3<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
+            else
+                hipLaunchKernelGGL((kb_collide<L, PR, MODEL, REP>), dim3((unsigned)blocks), dim3(kBlock), 0, s, D, n);
         }
         if constexpr (batch_fused_available<L, PR, MODEL, REP>()) {
             if (fblocks > 0) launch_batch_fused<PR, MODEL>(D, n, fblocks, fused_kinds, s);

@@ -614,6 +614,8 @@ def test_batch_one_pass_bitwise(M):
         (M.make_params(lattice=D3, precision=M.MIXED, nx=64, ny=12, nz=20, A=0.02, rho0_B=0.01, bc=(1, 1, 2)),
          None, 16, F),
         (M.make_params(lattice=D3, precision=M.MIXED, nx=64, ny=6, nz=8, A=0.02, rho0_B=0.01), None, 12, T),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=40, ny=10, nz=12, A=0.02, rho0_B=0.01, bc=(1, 0, 2)),
+         None, 14, T),
         (M.make_params(lattice=D3, model=M.SC_MC, precision=M.MIXED, nx=64, ny=8, nz=16, G_RB=1.2), None, 22, F),
         (M.make_params(lattice=D3, model=M.SC_MP, precision=M.FP32, nx=64, ny=8, nz=24, G=-5.0, rho0_R=1.9,
                        rho0_B=0.12), "scmp", 25, F),
