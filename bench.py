@@ -12,6 +12,7 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import math
@@ -26,10 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D3Q19 CG MLUPS + % HBM roofline at 256^3; sweep-serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# what the fused step's machine code and its memory layout are made from: its sources, the
-# library source that lays out the population arrays, and the build flags
-KERNEL_SOURCES = ["csrc/node.hpp", "csrc/kernels.hpp", "csrc/fused.hpp", "csrc/lattice.hpp", "csrc/mclbm.hip",
-                  "_build.py"]
+# what the step's machine code and its memory layout are made from: every source of the
+# library (not the stream probe) and the build flags
+KERNEL_SOURCES = sorted(os.path.relpath(f, os.path.join(ROOT, "paper_2110_05197_amd"))
+                        for f in glob.glob(os.path.join(ROOT, "paper_2110_05197_amd", "csrc", "*"))
+                        if not f.endswith("stream_probe.hip")) + ["_build.py"]
 
 
 def kernel_hash() -> str:
