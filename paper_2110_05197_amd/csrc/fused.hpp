@@ -440,12 +440,18 @@ struct FusedShape {
 // TY = 8 when ny allows, else 4; TZ planes per block.  FP64 (wide) tiles are
 // 4 rows: half the threads, so that each wave may hold its double-precision
 // planes in up to 512 registers and the LDS slot of plane z+1 stays at the
-// FP32 size.
+// FP32 size.  Where 96 divides nx and 64 does not (nx = 96, 288, ...), the
+// columns are 96 x 4 instead (six waves, no lane idle), in place of 64-wide
+// columns whose last one would leave a third of its lanes or more idle.
 inline bool fused_shape(const KParams &P, FusedShape &sh, bool wide = false)
 {
     sh.tx = 64;
     sh.ragged = P.nx % 64 != 0;
-    if (!wide && P.ny % 8 == 0) sh.ty = 8;
+    if (!wide && P.nx % 96 == 0 && P.nx % 64 != 0 && P.ny % 4 == 0) {
+        sh.tx = 96;
+        sh.ty = 4;
+        sh.ragged = false;
+    } else if (!wide && P.ny % 8 == 0) sh.ty = 8;
     else if (P.ny % 4 == 0) sh.ty = 4;
     else return false;
     // z-chunk: at most one block per compute unit (256 on MI355X) -- more
@@ -499,6 +505,12 @@ void launch_fused(const KParams &P, const void *src, void *dst, unsigned *flag, 
 {
     FusedShape sh;
     fused_shape(P, sh, PR == 0);  // checked at create time
+    if constexpr (PR != 0) {
+        if (sh.tx == 96) {
+            launch_fused_shape<PR, MODEL, 96, 4, false>(P, src, dst, flag, sh.tz, s);
+            return;
+        }
+    }
     if (sh.ty == 4) {
         if (sh.ragged) launch_fused_shape<PR, MODEL, 64, 4, true>(P, src, dst, flag, sh.tz, s);
         else launch_fused_shape<PR, MODEL, 64, 4, false>(P, src, dst, flag, sh.tz, s);

@@ -123,9 +123,9 @@ def test_cg_d3q19_fp32(M, orc, kernel):
 
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_cg_d3q19_fp32_density_ratio_tile_shapes(M, orc, kernel):
-    # nx = 96: a 64-wide column and a masked 32-wide edge column; ny = 20: 4-row tiles
-    shape = (18, 20, 96)
-    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=96, ny=20, nz=18, A=0.02,
+    # nx = 80: a 64-wide column and a masked 16-wide edge column; ny = 20: 4-row tiles
+    shape = (18, 20, 80)
+    p = M.make_params(lattice=M.D3Q19, precision=M.FP32, nx=80, ny=20, nz=18, A=0.02,
                       rho0_B=0.1, tau_R=0.8, tau_B=1.0)
     rR, rB, u = cg_droplet_case(shape, 15, gamma=10.0)
     compare(M, orc, p, rR, rB, u, 100, 2e-5, kernel=kernel, label="cg-d3q19-fp32-gamma10")
@@ -215,6 +215,57 @@ def test_deep_march_fused_equals_two_pass_bitwise(M, prec):
         s2, f2 = gpu_run(M, p, rR, rB, u, 29, kernel=2)
         assert s2.fused_tile()[2] >= 8
         assert np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("prec,bc,tol", [(1, (0, 0, 0), 2e-5), (2, (1, 1, 2), 2e-5)])
+def test_cg_96_wide_columns(M, orc, prec, bc, tol):
+    """nx = 96 (96 divides it, 64 does not): one column of 96 x 4 per row
+    band instead of a 64-wide column and a half-idle masked one; 96 x 96 x 80,
+    24 columns x 10 z-chunks of 8 planes, 100 steps against the oracle."""
+    shape = (80, 96, 96)
+    p = M.make_params(lattice=M.D3Q19, precision=prec, nx=96, ny=96, nz=80, bc=bc, A=0.02,
+                      rho0_B=0.1, tau_R=0.8, tau_B=1.0)
+    rR, rB, u = cg_droplet_case(shape, 44, gamma=10.0)
+    sim = M.Sim(p)
+    assert sim.kernel_used() == M.KERNEL_FUSED
+    tx, ty, planes = sim.fused_tile()
+    say(f"[96-wide] prec={prec} bc={bc}: {tx}x{ty} columns, {planes} planes per block")
+    assert (tx, ty) == (96, 4) and planes >= 8
+    sim.close()
+    compare(M, orc, p, rR, rB, u, 100, tol, label="cg-96-wide")
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+@pytest.mark.parametrize("model", ["CG", "SC_MP", "SC_MC"])
+def test_96_wide_columns_equal_two_pass_bitwise(M, prec, model):
+    """The 96 x 4 columns of the one-pass kernel equal the two-pass kernels
+    bit for bit, every model, periodic and walls + outflow (and, for the
+    colour gradient in FP32 and mixed, with conserve_mass)."""
+    shape = (40, 96, 96)
+    for bc in ((0, 0, 0), (1, 1, 2)):
+        if model == "SC_MP":
+            p = M.make_params(lattice=M.D3Q19, model=M.SC_MP, precision=prec, nx=96, ny=96, nz=40, bc=bc,
+                              G=-5.0, rho0_R=1.9, rho0_B=0.12)
+            a, b = inputs.droplet(shape, 20.0, 1.9, 0.12)
+            rR, rB, u = a + b, None, None
+        elif model == "SC_MC":
+            p = M.make_params(lattice=M.D3Q19, model=M.SC_MC, precision=prec, nx=96, ny=96, nz=40, bc=bc,
+                              G_RB=1.2)
+            rR, rB, u = cg_droplet_case(shape, 45, gamma=1.0)
+        else:
+            p = M.make_params(lattice=M.D3Q19, precision=prec, nx=96, ny=96, nz=40, bc=bc, A=0.02,
+                              rho0_B=0.1, tau_R=0.8, tau_B=1.0)
+            rR, rB, u = cg_droplet_case(shape, 46, gamma=10.0)
+        cons = (0, 1) if model == "CG" and prec in (1, 2) else (0,)
+        for c in cons:
+            q = dict(p, conserve_mass=c)
+            say(f"[bitwise 96-wide] model={model} prec={prec} bc={bc} conserve_mass={c}")
+            s1, f1 = gpu_run(M, q, rR, rB, u, 17, kernel=1)
+            s2, f2 = gpu_run(M, q, rR, rB, u, 17, kernel=2)
+            assert s2.fused_tile()[:2] == (96, 4) and s2.fused_tile()[2] >= 4
+            assert np.array_equal(f1, f2)
+            s1.close()
+            s2.close()
 
 
 # --------------------------------------------------------------------------
