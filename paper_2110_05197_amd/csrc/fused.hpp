@@ -300,10 +300,11 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
 // (D3Q19, ny a multiple of the column height) in one launch per kind; a
 // block finds its simulation in the descriptor array (one-pass block ranges),
 // skips it unless it is running and of the launch's kind (all faces periodic
-// or not; nx a multiple of 64 or not), and processes one column of that
-// simulation.  EDGE launches take the simulations whose nx is not a multiple
-// of 64 and run every column through the masked column body (the last column
-// in x holds nx mod 64 nodes; a full column computes the same as unmasked).
+// or not; nx a multiple of 64 or not; 96-wide columns or not), and processes
+// one column of that simulation.  EDGE launches take the simulations whose nx
+// is not a multiple of 64 and run every column through the masked column body
+// (the last column in x holds nx mod 64 nodes; a full column computes the same
+// as unmasked); WIDE launches take those on 96 x 4 columns.
 // The per-node arithmetic is the solo kernels', so a batched simulation
 // evolves bitwise as it would alone.  Columns: 64-wide rows (at 16
 // or 32 nodes the rows of the x-shifted pushes split cache lines between
@@ -314,12 +315,38 @@ __global__ __launch_bounds__(TX *TY) void k_fused(KParams P, const typename Prec
 // faster than the batched two-pass kernels.
 constexpr int kBatchTX = 64;
 constexpr int batch_ty(int precision) { return precision == 0 || precision == 2 ? 4 : 8; }
-// which kernels a group launches: all-periodic sims and others, each with nx
-// a multiple of 64 or not (EDGE)
-constexpr int kFusedPeriodic = 1, kFusedBounded = 2, kFusedPeriodicEdge = 4, kFusedBoundedEdge = 8;
-constexpr int fused_kind(bool periodic, bool edge)
+// As in the solo kernel, a simulation whose nx 96 divides and 64 does not
+// takes 96 x 4 columns (kernels of their own, WIDE): no lane idles where a
+// 64-wide split would leave half of its last column empty.  Not FP64, nor the
+// mixed-precision colour gradient: a six-wave block allows 256 registers a
+// lane, and their batched columns (which ask each simulation whether to keep
+// colour mass) need more (FP64 about 400; mixed 40 spilled).
+constexpr int kBatchWideTX = 96, kBatchWideTY = 4;
+constexpr bool batch_wide_kernel(int precision, int model)
 {
-    return edge ? (periodic ? kFusedPeriodicEdge : kFusedBoundedEdge) : (periodic ? kFusedPeriodic : kFusedBounded);
+    return precision != 0 && !(precision == 2 && model == CG);
+}
+constexpr bool batch_wide(int precision, int model, int nx, int ny)
+{
+    return batch_wide_kernel(precision, model) && nx % kBatchWideTX == 0 && nx % kBatchTX != 0
+           && ny % kBatchWideTY == 0;
+}
+constexpr int batch_tile_tx(int precision, int model, int nx, int ny)
+{
+    return batch_wide(precision, model, nx, ny) ? kBatchWideTX : kBatchTX;
+}
+constexpr int batch_tile_ty(int precision, int model, int nx, int ny)
+{
+    return batch_wide(precision, model, nx, ny) ? kBatchWideTY : batch_ty(precision);
+}
+// which kernels a group launches: all-periodic sims and others, each with nx
+// a multiple of 64 or not (EDGE), or on 96 x 4 columns (WIDE)
+constexpr int kFusedPeriodic = 1, kFusedBounded = 2, kFusedPeriodicEdge = 4, kFusedBoundedEdge = 8;
+constexpr int kFusedPeriodicWide = 16, kFusedBoundedWide = 32;
+constexpr int fused_kind(bool periodic, bool edge, bool wide)
+{
+    return wide ? (periodic ? kFusedPeriodicWide : kFusedBoundedWide)
+           : edge ? (periodic ? kFusedPeriodicEdge : kFusedBoundedEdge) : (periodic ? kFusedPeriodic : kFusedBounded);
 }
 
 __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long b)
@@ -332,25 +359,30 @@ __device__ __forceinline__ int find_sim_fused(const SimDesc *D, int n, long long
     return lo;
 }
 
-template <int PR, int MODEL, bool PERIODIC, bool EDGE>
-__global__ __launch_bounds__(kBatchTX *batch_ty(PR)) void kb_fused(SimDesc *D, int nsims)
+constexpr int kb_tx(bool wide) { return wide ? kBatchWideTX : kBatchTX; }
+constexpr int kb_ty(int precision, bool wide) { return wide ? kBatchWideTY : batch_ty(precision); }
+
+template <int PR, int MODEL, bool PERIODIC, bool EDGE, bool WIDE = false>
+__global__ __launch_bounds__(kb_tx(WIDE) * kb_ty(PR, WIDE)) void kb_fused(SimDesc *D, int nsims)
 {
-    constexpr int kBatchTY = batch_ty(PR);
+    static_assert(!(WIDE && EDGE) && !(WIDE && !batch_wide_kernel(PR, MODEL)), "96-wide columns: full columns");
+    constexpr int TX = kb_tx(WIDE), TY = kb_ty(PR, WIDE);
     extern __shared__ __align__(16) unsigned char smem[];
     const int s = find_sim_fused(D, nsims, blockIdx.x);
     const SimDesc &d = D[s];
     if (d.state != 0) return;
     if ((d.P.bc[0] == 0 && d.P.bc[1] == 0 && d.P.bc[2] == 0) != PERIODIC) return;
-    if ((d.P.nx % kBatchTX != 0) != EDGE) return;
+    if (batch_wide(PR, MODEL, d.P.nx, d.P.ny) != WIDE) return;
+    if (!WIDE && (d.P.nx % kBatchTX != 0) != EDGE) return;
     const long long b = blockIdx.x - d.fblock0;
-    const int tiles_x = (d.P.nx + kBatchTX - 1) / kBatchTX, tiles_y = d.P.ny / kBatchTY;
+    const int tiles_x = (d.P.nx + TX - 1) / TX, tiles_y = d.P.ny / TY;
     const int bx = (int)(b % tiles_x), by = (int)((b / tiles_x) % tiles_y), bz = (int)(b / ((long long)tiles_x * tiles_y));
-    const int x0 = bx * kBatchTX, y0 = by * kBatchTY, z0 = bz * d.ftz, z1 = min(z0 + d.ftz, d.P.nz);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * d.ftz, z1 = min(z0 + d.ftz, d.P.nz);
     using S = typename Prec<PR>::S;
     const S *src = global_ptr<const S>(d.f[d.cur]);
     S *dst = global_ptr<S>(d.f[d.cur ^ 1]);
     unsigned *flag = global_ptr<unsigned>(d.flag);
-    fused_column<PR, MODEL, kBatchTX, kBatchTY, PERIODIC, EDGE>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
+    fused_column<PR, MODEL, TX, TY, PERIODIC, EDGE>(d.P, src, dst, flag, x0, y0, z0, z1, smem);
 }
 
 // Planes per column of the batched simulations of a group.  A column
@@ -389,8 +421,8 @@ inline int batch_group_tz(const long long *cols, const int *nz, int n, long long
     return best;
 }
 
-// Blocks of kb_fused<PR, MODEL, *, *> the device holds at once (the smallest
-// over the four kinds).
+// Blocks of kb_fused<PR, MODEL, ...> the device holds at once (the smallest
+// over the kinds).
 template <int PR, int MODEL>
 long long batch_fused_resident()
 {
@@ -408,10 +440,24 @@ long long batch_fused_resident()
             return 256;
         per_cu = std::min(per_cu, b);
     }
+    if constexpr (batch_wide_kernel(PR, MODEL)) {
+        constexpr int lds_w = fused_lds_bytes<PR, MODEL, kBatchWideTX, kBatchWideTY>();
+        const void *wide[2] = {(const void *)kb_fused<PR, MODEL, true, false, true>,
+                               (const void *)kb_fused<PR, MODEL, false, false, true>};
+        for (const void *fn : wide) {
+            int b = 0;
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_w);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, kBatchWideTX * kBatchWideTY, lds_w) != hipSuccess)
+                return 256;
+            per_cu = std::min(per_cu, b);
+        }
+    }
     return (long long)std::max(1, per_cu) * std::max(1, cus);
 }
 
-// kinds: the fused_kind() bits of the simulations present.
+// kinds: the fused_kind() bits of the simulations present.  Every launch
+// covers the group's whole one-pass block range; a block whose simulation is
+// of another kind returns at once.
 template <int PR, int MODEL>
 void launch_batch_fused(SimDesc *D, int n, long long fblocks, int kinds, hipStream_t s)
 {
@@ -428,6 +474,22 @@ void launch_batch_fused(SimDesc *D, int n, long long fblocks, int kinds, hipStre
     if (kinds & kFusedBounded) hipLaunchKernelGGL((kb_fused<PR, MODEL, false, false>), grid, block, lds, s, D, n);
     if (kinds & kFusedPeriodicEdge) hipLaunchKernelGGL((kb_fused<PR, MODEL, true, true>), grid, block, lds, s, D, n);
     if (kinds & kFusedBoundedEdge) hipLaunchKernelGGL((kb_fused<PR, MODEL, false, true>), grid, block, lds, s, D, n);
+    if constexpr (batch_wide_kernel(PR, MODEL)) {
+        constexpr int lds_w = fused_lds_bytes<PR, MODEL, kBatchWideTX, kBatchWideTY>();
+        static bool attr_w = false;
+        if (!attr_w) {
+            (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL, true, false, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_w);
+            (void)hipFuncSetAttribute((const void *)kb_fused<PR, MODEL, false, false, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_w);
+            attr_w = true;
+        }
+        const dim3 block_w(kBatchWideTX * kBatchWideTY);
+        if (kinds & kFusedPeriodicWide)
+            hipLaunchKernelGGL((kb_fused<PR, MODEL, true, false, true>), grid, block_w, lds_w, s, D, n);
+        if (kinds & kFusedBoundedWide)
+            hipLaunchKernelGGL((kb_fused<PR, MODEL, false, false, true>), grid, block_w, lds_w, s, D, n);
+    }
 }
 
 struct FusedShape {

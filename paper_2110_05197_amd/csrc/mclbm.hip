@@ -139,7 +139,8 @@ bool auto_prefers_fused(const mclbm_params &p)
     return p.lattice != MCLBM_D2Q9 || (long long)p.nx * p.ny >= (1LL << 19);
 }
 
-// The batched one-pass kernel takes 64 x batch_ty columns, the last one in x
+// The batched one-pass kernel takes 96 x 4 columns where 96 divides nx and
+// 64 does not (batch_wide), else 64 x batch_ty columns, the last one in x
 // masked when 64 does not divide nx, as long as at least three quarters of
 // the columns' lanes hold nodes (measured against the batched two-pass
 // kernels, FP32: nx = 112 1.17x, 96 and 48 1.05-1.08x, 144 and 160 1.01-1.06x;
@@ -149,9 +150,17 @@ bool auto_prefers_fused(const mclbm_params &p)
 // one-pass kernel for this lattice, model and precision).
 bool batch_fused_ok(const mclbm_params &p, long long resident)
 {
+    if (resident <= 0 || multirange_of(p) || p.kernel == MCLBM_KERNEL_TWO_PASS) return false;
+    if (batch_wide(p.precision, p.model, p.nx, p.ny)) return true;
     const long long lanes = (long long)kBatchTX * ((p.nx + kBatchTX - 1) / kBatchTX);
-    return resident > 0 && !multirange_of(p) && p.kernel != MCLBM_KERNEL_TWO_PASS
-           && p.ny % batch_ty(p.precision) == 0 && 4LL * p.nx >= 3 * lanes;
+    return p.ny % batch_ty(p.precision) == 0 && 4LL * p.nx >= 3 * lanes;
+}
+
+// Columns per plane of a batched one-pass simulation.
+long long batch_fused_columns(const mclbm_params &p)
+{
+    const int tx = batch_tile_tx(p.precision, p.model, p.nx, p.ny), ty = batch_tile_ty(p.precision, p.model, p.nx, p.ny);
+    return (long long)((p.nx + tx - 1) / tx) * (p.ny / ty);
 }
 
 mclbm_status validate(const mclbm_params *p)
@@ -983,7 +992,7 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
         for (int idx : groups[key]) {
             const mclbm_params &q = sims[idx]->prm;
             if (batch_fused_ok(q, resident)) {
-                fcols.push_back((long long)((q.nx + kBatchTX - 1) / kBatchTX) * (q.ny / batch_ty(q.precision)));
+                fcols.push_back(batch_fused_columns(q));
                 fnz.push_back(q.nz);
             }
         }
@@ -1004,12 +1013,12 @@ mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t
             d.fblock0 = g.fblocks;
             if (batch_fused_ok(s->prm, resident)) {
                 d.ftz = batch_fused_tz(s->prm.nz, group_tz);
-                d.fnblocks = (long long)((s->prm.nx + kBatchTX - 1) / kBatchTX)
-                             * (s->prm.ny / batch_ty(s->prm.precision)) * ((s->prm.nz + d.ftz - 1) / d.ftz);
+                d.fnblocks = batch_fused_columns(s->prm) * ((s->prm.nz + d.ftz - 1) / d.ftz);
                 g.fblocks += d.fnblocks;
                 const bool periodic = s->prm.bc[0] == MCLBM_PERIODIC && s->prm.bc[1] == MCLBM_PERIODIC
                                       && s->prm.bc[2] == MCLBM_PERIODIC;
-                g.fused_kinds |= fused_kind(periodic, s->prm.nx % kBatchTX != 0);
+                g.fused_kinds |= fused_kind(periodic, s->prm.nx % kBatchTX != 0,
+                                            batch_wide(s->prm.precision, s->prm.model, s->prm.nx, s->prm.ny));
             } else {
                 d.nblocks = grid_of(s->kp.N);
                 g.blocks += d.nblocks;

@@ -649,9 +649,11 @@ def test_batch_one_pass_bitwise(M):
     models, walls and outflow, periodic and bounded sims of one group, nx a
     multiple of 64 or not (masked last column where at least 3/4 of the
     columns' lanes hold nodes: 48, 52, 100, 112, 120 and 200 = 3 x 64 + 8; two-pass
-    below that: 3, 40, 130), so up to four launches of the one-pass kernel per group,
-    z-chunks with a shorter last chunk (nz = 101 is prime: every chunk length
-    above one leaves a remainder)."""
+    below that: 3, 40, 130; 96 x 4 columns at nx = 96, except FP64 and the mixed
+    colour gradient, which take a 64-wide and a masked column), so up to six
+    launches of the one-pass kernel per group, z-chunks with a shorter last
+    chunk (nz = 101 is prime: every chunk length above one leaves a
+    remainder)."""
     def sc_mp(shape):
         a, b = inputs.droplet(shape, 3.0, 1.9, 0.12)
         return a + b, None, None
@@ -680,6 +682,13 @@ def test_batch_one_pass_bitwise(M):
         (M.make_params(lattice=D3, precision=M.FP64, nx=100, ny=8, nz=10, A=0.02, bc=(0, 1, 0)), None, 10, F),
         (M.make_params(lattice=D3, precision=M.MIXED, nx=100, ny=8, nz=12, A=0.02, rho0_B=0.01), None, 12, F),
         (M.make_params(lattice=D3, precision=M.FP16, nx=52, ny=8, nz=10, A=0.02, bc=(2, 0, 1)), None, 8, F),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=96, ny=8, nz=12, A=0.01), None, 10, F),
+        (M.make_params(lattice=D3, precision=M.FP32, nx=96, ny=12, nz=10, A=0.01, bc=(1, 1, 2)), None, 9, F),
+        (M.make_params(lattice=D3, precision=M.FP16, nx=96, ny=4, nz=14, A=0.02, bc=(0, 1, 0)), None, 8, F),
+        (M.make_params(lattice=D3, precision=M.MIXED, nx=96, ny=8, nz=10, A=0.02, rho0_B=0.01), None, 11, F),
+        (M.make_params(lattice=D3, model=M.SC_MC, precision=M.MIXED, nx=96, ny=8, nz=12, G_RB=1.2,
+                       bc=(1, 0, 2)), None, 9, F),
+        (M.make_params(lattice=D3, precision=M.FP64, nx=96, ny=8, nz=8, A=0.02), None, 7, F),
         (M.make_params(lattice=D3, model=M.SC_MP, precision=M.FP32, nx=48, ny=8, nz=16, G=-5.0, rho0_R=1.9,
                        rho0_B=0.12), "scmp", 13, F),
         (M.make_params(lattice=D3, model=M.SC_MC, precision=M.FP64, nx=112, ny=8, nz=10, G_RB=1.2,
