@@ -344,9 +344,11 @@ mclbm_status mclbm_fused_tile(const mclbm_sim *sim, int32_t *tx, int32_t *ty, in
  * precision), and whose kernel is not MCLBM_KERNEL_TWO_PASS, step in batched
  * one-pass launches (64 x 8 columns, 64 x 4 in FP64 and mixed precision, the
  * last column in x masked when 64 does not divide nx, which the batch does
- * when nx >= 3/4 of 64 * ceil(nx / 64); z-chunks sized for the group; one
- * launch per kind present in the group: all faces periodic or not, nx a
- * multiple of 64 or not); the others in batched two-pass launches.  The
+ * when nx >= 3/4 of 64 * ceil(nx / 64); 96 x 4 columns, with ny % 4 == 0,
+ * where 96 divides nx and 64 does not, except in FP64 and for the mixed
+ * colour gradient; z-chunks sized for the group; one launch per kind present
+ * in the group: all faces periodic or not, nx a multiple of 64 or not, 96-wide
+ * columns or not); the others in batched two-pass launches.  The
  * per-node arithmetic is the same as mclbm_step's, so a sim's result is
  * bitwise the same alone (either kernel) and in any batch. */
 mclbm_status mclbm_batch_create(mclbm_sim *const *sims, int32_t n, const int64_t *target_steps,
