@@ -414,10 +414,12 @@ __global__ void k_fill_int(int *__restrict__ a, long long n, int v)
 // Connected components of the inside nodes under face adjacency (periodic
 // axes wrap), by alternating launches of min-label propagation and pointer
 // jumping.  A label is always the index of a node of the same component and
-// never increases; when neither pass changes anything, every node carries
-// the smallest index of its component.  Each label has a single writer (its
-// own node); a neighbour's label read during an update is its old or new
-// value, both valid.
+// never increases: every write is an atomic minimum.  A node that lowers its
+// label from l to m also lowers node l's label to m, which carries every node
+// labelled l along at its next jump; the jump follows labels while they
+// decrease (each step lowers the label, so the walk ends).  When neither pass
+// changes anything, every node carries the smallest index of its component.
+// A label read during an update is an old or a new value, both valid.
 __device__ __forceinline__ long long face_neighbour(const KParams &P, int x, int y, int z, int axis, int dir)
 {
     int c[3] = {x, y, z};
@@ -447,7 +449,8 @@ __global__ __launch_bounds__(256) void k_ccl_prop(KParams P, int *__restrict__ l
             if (v >= 0 && v < m) m = v;
         }
     if (m < l) {
-        lab[n] = m;
+        atomicMin(&lab[n], m);
+        atomicMin(&lab[l], m);
         atomicOr(changed, 1u);
     }
 }
@@ -458,9 +461,14 @@ __global__ __launch_bounds__(256) void k_ccl_jump(long long N, int *__restrict__
     if (n >= N) return;
     const int l = lab[n];
     if (l < 0) return;
-    const int ll = lab[l];
-    if (ll < l) {
-        lab[n] = ll;
+    int r = l;
+    for (;;) {   // r strictly decreases: at most l steps
+        const int rr = lab[r];
+        if (rr < 0 || rr >= r) break;
+        r = rr;
+    }
+    if (r < l) {
+        atomicMin(&lab[n], r);
         atomicOr(changed, 1u);
     }
 }
