@@ -180,9 +180,11 @@ def cpu_baseline(rR, rB, n: int, steps: int, steps_one_thread: int):
                 cpu_model=cpu_model(), build="gcc -O3 -march=native -fopenmp -ffp-contract=off")
 
 
-def serving_leg(full: bool):
+def serving_leg(full: bool, conserve: bool = False):
     """Sweep serving: continuous batching (FP32 / mixed, batched graphs) against
-    one-at-a-time FP64 solves of the same seeded trace on the same GPU."""
+    one-at-a-time FP64 solves of the same seeded trace on the same GPU.
+    conserve: the batched FP32 / mixed colour-gradient requests keep each
+    colour's node mass to one rounding per step."""
     from paper_2110_05197_amd import serve
     if full:
         kw = dict(n=256)
@@ -199,7 +201,7 @@ def serving_leg(full: bool):
     log = (lambda s: print(s, file=sys.stderr, flush=True)) if full else None
     runs = {}
     for rule in ("fp64", "gamma"):
-        trace = serve.make_trace(seed=0, precision_rule=rule, **kw)
+        trace = serve.make_trace(seed=0, precision_rule=rule, conserve_mass=conserve, **kw)
         done, wall = serve.Server(k_steps=100, log=log, keep_fields=True).run(trace)
         runs[rule] = (done, serve.summarize(done, wall))
         print(f"[bench] batched ({rule} rule): {runs[rule][1]}", file=sys.stderr, flush=True)
@@ -208,7 +210,7 @@ def serving_leg(full: bool):
     fifo = serve.summarize(done2, wall2)
     print(f"[bench] one-at-a-time FP64: {fifo}", file=sys.stderr, flush=True)
     by2 = {r.rid: r for r in done2}
-    out = dict(trace=desc, trace_is_full=full, one_at_a_time_fp64=fifo,
+    out = dict(trace=desc, trace_is_full=full, conserve_mass=conserve, one_at_a_time_fp64=fifo,
                accuracy_metrics="per request, batched result against its FP64 solve at the final step: "
                                 "rho_err = relative max-norm error of rho_R and rho_B; volume_err, jump_err = "
                                 "relative difference of the red volume and of the density jump rho_in - rho_out "
@@ -331,7 +333,8 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serve the full 256-request trace (minutes) instead of the reduced one")
     ap.add_argument("--conserve-mass", action="store_true",
-                    help="CG, FP32 or mixed storage: keep each colour's node mass to one rounding per step")
+                    help="CG, FP32 or mixed storage: keep each colour's node mass to one rounding per step "
+                         "(the benchmark step and the batched serving requests)")
     ap.add_argument("--next-rows", action="store_true",
                     help="time the multirange Shan-Chen step and the interface observables on the workload")
     ap.add_argument("--copy-probe", action="store_true",
@@ -454,7 +457,7 @@ def main():
 
     serving = None
     if not args.no_serve:
-        serving = serving_leg(args.serve_full)
+        serving = serving_leg(args.serve_full, args.conserve_mass)
 
     dtype = {0: "f64", 1: "f32", 2: "f32+f64", 3: "f16-storage/f32"}[args.precision]
     out = {

@@ -133,7 +133,7 @@ def sc_coupling_for_ratio(gamma: float) -> float:
 
 def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 512),
                d3_sizes=(64, 80, 96, 112, 128, 144, 160), steps_range=(1000, 20000),
-               precisions=(1, 2), precision_rule="fp64"):
+               precisions=(1, 2), precision_rule="fp64", conserve_mass=False):
     """Seeded request trace: Poisson arrivals at `rate` per second; model CG
     or SC (p = 1/2); droplet (R = L/4) or ligament (R = L/8, aspect 5, capped
     to 0.8 L); D2Q9 or D3Q19 (p = 1/2) with L from the size lists; density
@@ -144,7 +144,10 @@ def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 5
     density and the spurious currents drift away from the FP64 solution over
     thousands of steps); "gamma": FP32 below 100 and mixed from 100 on;
     "random": drawn from `precisions`.  The draw is made under every rule,
-    so the traces differ in precision only."""
+    so the traces differ in precision only.  conserve_mass: the FP32 and
+    mixed colour-gradient requests keep each colour's node mass to one
+    rounding per step (mclbm_params.conserve_mass), which brings their
+    densities closer to the FP64 solves at a few per cent of the step."""
     import paper_2110_05197_amd as M
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -173,7 +176,8 @@ def make_trace(n=256, rate=20.0, seed=0, d2_sizes=(64, 96, 128, 192, 256, 384, 5
         nuR, nuB = nu0 * math.sqrt(nu_ratio), nu0 / math.sqrt(nu_ratio)
         if model == "CG":
             p = M.make_params(model=M.CG, rho0_R=gamma, rho0_B=1.0, tau_R=0.5 + 3 * nuR,
-                              tau_B=0.5 + 3 * nuB, **base)
+                              tau_B=0.5 + 3 * nuB,
+                              conserve_mass=int(conserve_mass and prec in (M.FP32, M.MIXED)), **base)
             p = M.params_from_sigma(p, sigma)
         else:
             G = sc_coupling_for_ratio(gamma) if gamma > 1.5 else -4.5

@@ -86,6 +86,21 @@ def test_trace_precision_rule():
         serve.make_trace(seed=5, n=4, precision_rule="fp16")
 
 
+def test_trace_conserve_mass_option():
+    """conserve_mass=True marks exactly the FP32 and mixed colour-gradient
+    requests (FP64 and Shan-Chen requests keep 0) and changes nothing else."""
+    import paper_2110_05197_amd as M
+    for rule in ("fp64", "gamma"):
+        a = serve.make_trace(seed=6, n=60, precision_rule=rule)
+        b = serve.make_trace(seed=6, n=60, precision_rule=rule, conserve_mass=True)
+        assert all(x.params["conserve_mass"] == 0 for x in a)
+        for x, y in zip(a, b):
+            want = int(x.params["model"] == M.CG and x.params["precision"] in (M.FP32, M.MIXED))
+            assert y.params["conserve_mass"] == want
+            assert dict(y.params, conserve_mass=0) == x.params and y.arrival == x.arrival
+        assert any(y.params["conserve_mass"] for y in b)
+
+
 def test_initial_fields_sc_at_coexistence():
     tr = serve.make_trace(seed=0, n=40, d2_sizes=(64,), d3_sizes=(32,))
     sc = [r for r in tr if r.params["model"] == 1]
